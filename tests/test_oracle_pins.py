@@ -1,0 +1,374 @@
+"""Pins of the CPU oracle to facts the paper and mathematics fix.
+
+Every pin compares the oracle (Fast PIMD-B, Alg. 1) with something that is
+not the oracle: values the paper prints (N = 3 example), brute force over
+all N! permutations with the representative map, the composition expansion
+of the recurrence, the original cubic algorithm (Alg. 2), autograd through
+the potential, the definitional backward potentials, closed forms (N = 1,
+N = 2, uniform and widely separated configurations) and invariants.
+"""
+import itertools
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2305_18025_amd.inputs import cube_system, gaussian_system, omega_p
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _parse_cycles(s):
+    return [tuple(int(ch) for ch in grp) for grp in s.strip("()").split(")(")]
+
+
+def _rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def _fmax_rel(F, G):
+    return np.abs(F - G).max() / max(np.abs(G).max(), 1e-300)
+
+
+# ----------------------------------------------------------------- paper values
+def test_cycle_notation_and_representatives_from_paper(oracle_lib):
+    from oracle import brute
+    g = json.load(open(os.path.join(GOLDEN, "paper_n3.json")))
+    for two_line, cyc in g["two_line_to_cycles"].items():
+        sigma = tuple(int(x) for x in two_line.split(","))
+        got = "".join("(" + "".join(map(str, c)) + ")" for c in brute.cycles(sigma))
+        assert got == cyc
+    for src, rep in g["representatives"].items():
+        sigma = brute.from_cycles(_parse_cycles(src), 3)
+        want = brute.from_cycles(_parse_cycles(rep), 3)
+        assert brute.representative(sigma) == want, src
+
+
+def test_n3_expansion_weights_and_potential(oracle_lib):
+    """e^{-beta V} = 1/6 e^{-beta E(1)(2)(3)} + 1/3 e^{-beta E(123)} + 1/6 ... (paper's N=3 expansion)."""
+    from oracle import brute
+    g = json.load(open(os.path.join(GOLDEN, "paper_n3.json")))
+    R = gaussian_system(3, 4, seed=11, sigma_c=0.6)
+    beta, m = 0.8, 1.3
+    w = omega_p(4, beta)
+    k = 0.5 * m * w * w
+    # brute-force multiplicities / 3! reproduce the printed weights exactly
+    counts = brute.exchange(R, beta, m, w)["counts"]
+    for rep, (num, den) in g["weights"].items():
+        sigma = brute.from_cycles(_parse_cycles(rep), 3)
+        assert Fraction(counts[sigma], 6) == Fraction(num, den)
+    assert sum(counts.values()) == 6 and len(counts) == 4
+    z = 0.0
+    for rep, (num, den) in g["weights"].items():
+        sigma = brute.from_cycles(_parse_cycles(rep), 3)
+        z += num / den * math.exp(-beta * brute.perm_energy(R, sigma, k))
+    V = -math.log(z) / beta
+    o = oracle_lib.alg1(R, beta, m, w)
+    assert _rel(o["V"], V) < 1e-14
+
+
+def test_n3_connection_probability_grouping(oracle_lib):
+    """Pr[1->1], Pr[1->2] group the printed permutations; Pr[1->3] = 0."""
+    from oracle import brute
+    g = json.load(open(os.path.join(GOLDEN, "paper_n3.json")))
+    R = gaussian_system(3, 3, seed=12, sigma_c=0.5)
+    beta, m = 1.0, 1.0
+    w = omega_p(3, beta)
+    k = 0.5 * m * w * w
+    o = oracle_lib.alg1(R, beta, m, w)
+    ev = math.exp(-beta * o["V"])
+    for target, reps in g["pr_1_to"].items():
+        p = 0.0
+        for rep in reps:
+            num, den = g["weights"][rep]
+            sigma = brute.from_cycles(_parse_cycles(rep), 3)
+            p += num / den * math.exp(-beta * brute.perm_energy(R, sigma, k))
+        p /= ev
+        assert abs(o["Pr"][0, int(target) - 1] - p) < 1e-14
+    assert o["Pr"][0, 2] == 0.0
+
+
+def _partitions(n, largest=None):
+    if largest is None:
+        largest = n
+    if n == 0:
+        return 1
+    return sum(_partitions(n - p, p) for p in range(1, min(n, largest) + 1))
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7])
+def test_combinatorics_counts(N):
+    """2^(N-1) representatives; (N-1)! permutations with l -> l'; multiplicity
+    of each representative = N! / prod(block ends); cycle types = partitions."""
+    from oracle import brute, compositions
+    reps = {}
+    conn = np.zeros((N, N), dtype=np.int64)
+    types = set()
+    for sigma in itertools.permutations(range(1, N + 1)):
+        r = brute.representative(sigma)
+        reps[r] = reps.get(r, 0) + 1
+        for l in range(N):
+            conn[l, sigma[l] - 1] += 1
+        types.add(tuple(sorted(len(c) for c in brute.cycles(sigma))))
+        assert sorted(len(c) for c in brute.cycles(r)) == sorted(len(c) for c in brute.cycles(sigma))
+    assert len(reps) == 2 ** (N - 1)
+    assert (conn == math.factorial(N - 1)).all()
+    assert len(types) == _partitions(N)
+    # each composition of [1,N] is exactly one representative, weight prod 1/v_i
+    for blocks in compositions.compositions(N):
+        sigma = brute.from_cycles([tuple(range(u, v + 1)) for u, v in blocks], N)
+        assert Fraction(reps[sigma], math.factorial(N)) == math.prod(Fraction(1, v) for _, v in blocks)
+
+
+# ------------------------------------------------------ exact identities (brute)
+CASES = [(1, 2, 1.0, 0.0), (1, 5, 0.7, 0.0), (2, 2, 1.0, 0.0), (2, 4, 2.0, 0.0), (3, 2, 1.0, 0.0),
+         (4, 3, 0.5, 0.0), (5, 5, 1.0, 0.0), (6, 3, 1.5, 0.0), (7, 2, 1.0, 0.0), (5, 4, 1.0, 1.7),
+         (6, 3, 0.8, 2.3)]
+
+
+@pytest.mark.parametrize("N,P,beta,L", CASES)
+def test_alg1_matches_brute_force(oracle_lib, N, P, beta, L):
+    from oracle import brute
+    R = gaussian_system(N, P, seed=100 + 7 * N + P, sigma_c=0.45)
+    m = 1.2
+    w = omega_p(P, beta)
+    o = oracle_lib.alg1(R, beta, m, w, L=L)
+    b = brute.exchange(R, beta, m, w, L=L)
+    assert _rel(o["V"], b["V"]) < 1e-13
+    assert _fmax_rel(o["F"], b["F"]) < 1e-12
+    assert np.abs(o["Pr"] - b["Pr"]).max() < 1e-13
+
+
+@pytest.mark.parametrize("N,seed", [(8, 1), (10, 2), (12, 3)])
+def test_alg1_matches_composition_sum(oracle_lib, N, seed):
+    from oracle import compositions
+    R = gaussian_system(N, 4, seed=seed, sigma_c=0.5)
+    beta, m = 1.0, 1.0
+    w = omega_p(4, beta)
+    o = oracle_lib.alg1(R, beta, m, w)
+    c = compositions.exchange(R, beta, m, w)
+    assert _rel(o["V"], c["V"]) < 1e-13
+    assert np.abs(o["Pr"] - c["Pr"]).max() < 1e-12
+
+
+def test_tiny_config_matches_brute_force(oracle_lib):
+    """N=8, P=8 Gaussian configuration against all 8! permutations."""
+    from oracle import brute
+    from paper_2305_18025_amd.inputs import config_tiny
+    s = config_tiny()
+    o = oracle_lib.alg1(s.R, s.beta, s.m, s.omegaP)
+    b = brute.exchange(s.R, s.beta, s.m, s.omegaP)
+    assert _rel(o["V"], b["V"]) < 1e-13
+    assert _fmax_rel(o["F"], b["F"]) < 1e-12
+    assert np.abs(o["Pr"] - b["Pr"]).max() < 1e-13
+
+
+# ------------------------------------------------- a different algorithm (Alg. 2)
+@pytest.mark.parametrize("N,P,kind,L", [(16, 4, "g", 0.0), (33, 3, "c", 0.0), (48, 2, "g", 0.0),
+                                        (24, 5, "c", 3.0)])
+def test_alg1_matches_original_cubic_algorithm(oracle_lib, N, P, kind, L):
+    R = gaussian_system(N, P, seed=N, sigma_c=1.0) if kind == "g" else cube_system(N, P, seed=N)
+    beta, m = 1.0, 1.0
+    w = omega_p(P, beta)
+    o = oracle_lib.alg1(R, beta, m, w, L=L)
+    V2, F2 = oracle_lib.alg2(R, beta, m, w, L=L)
+    assert _rel(o["V"], V2) < 1e-12
+    assert _fmax_rel(o["F"], F2) < 1e-11
+
+
+@pytest.mark.parametrize("N,P,kind,L", [(40, 6, "g", 0.0), (96, 4, "c", 0.0), (64, 3, "c", 3.5)])
+def test_alg1_forces_match_autograd(oracle_lib, N, P, kind, L):
+    from oracle import autodiff
+    R = gaussian_system(N, P, seed=N + 1) if kind == "g" else cube_system(N, P, seed=N + 1)
+    beta, m = 1.0, 1.0
+    w = omega_p(P, beta)
+    o = oracle_lib.alg1(R, beta, m, w, L=L)
+    V, F = autodiff.exchange(R, beta, m, w, L=L)
+    assert _rel(o["V"], V) < 1e-12
+    assert _fmax_rel(o["F"], F) < 1e-10
+
+
+def test_backward_recursion_matches_definition(oracle_lib):
+    R = cube_system(40, 4, seed=9, side=2.0)
+    beta, m = 1.0, 1.0
+    w = omega_p(4, beta)
+    o = oracle_lib.alg1(R, beta, m, w)
+    vd = oracle_lib.backward_def(R, beta, m, w)
+    N = 40
+    assert np.abs(o["Vb"][1:N + 1] - vd[1:]).max() / abs(o["V"]) < 1e-13
+    assert _rel(o["Vb"][1], o["V"]) < 1e-13  # V^[1,N] from both recursions
+    assert o["Vb"][N + 1] == 0.0 and o["Vf"][0] == 0.0
+
+
+def test_finite_differences(oracle_lib):
+    R = gaussian_system(12, 5, seed=21, sigma_c=0.7)
+    beta, m = 1.0, 1.0
+    w = omega_p(5, beta)
+    o = oracle_lib.alg1(R, beta, m, w)
+    rng = np.random.default_rng(0)
+    h = 1e-5
+    for _ in range(12):
+        l, j, c = rng.integers(12), rng.integers(5), rng.integers(3)
+        Rp = R.copy(); Rp[l, j, c] += h
+        Rm = R.copy(); Rm[l, j, c] -= h
+        fd = -(oracle_lib.alg1(Rp, beta, m, w, extras=False, forces=False)["V"]
+               - oracle_lib.alg1(Rm, beta, m, w, extras=False, forces=False)["V"]) / (2 * h)
+        assert abs(fd - o["F"][l, j, c]) < 1e-6 * max(1.0, np.abs(o["F"]).max())
+
+
+# ------------------------------------------------------------- invariants
+@pytest.mark.parametrize("kind", ["gauss", "cube", "dense"])
+def test_probability_invariants(oracle_lib, kind):
+    N, P = 64, 4
+    if kind == "gauss":
+        R = gaussian_system(N, P, seed=5)
+    elif kind == "cube":
+        R = cube_system(N, P, seed=5)
+    else:
+        R = cube_system(N, P, seed=5, side=1.0)
+    o = oracle_lib.alg1(R, 1.0, 1.0, omega_p(P, 1.0))
+    Pr = o["Pr"]
+    assert np.abs(Pr.sum(axis=1) - 1).max() < 1e-12  # every l has one successor
+    assert np.abs(Pr.sum(axis=0) - 1).max() < 1e-12  # every u has one predecessor
+    # the direct-link formula subtracts potentials of size |V|, so a link
+    # probability that is zero in exact arithmetic may round to -ulp(|V|)
+    tol = 64 * np.finfo(float).eps * abs(o["V"])
+    assert (Pr >= -tol).all() and (Pr <= 1 + tol).all()
+    assert np.count_nonzero(np.triu(Pr, 2)) == 0  # Pr[l -> u] = 0 for u > l+1
+
+
+def test_forces_sum_to_zero(oracle_lib):
+    for L in (0.0, 4.0):
+        R = cube_system(50, 6, seed=3)
+        o = oracle_lib.alg1(R, 1.0, 1.0, omega_p(6, 1.0), L=L)
+        tot = o["F"].sum(axis=(0, 1))
+        assert np.abs(tot).max() < 1e-10 * np.abs(o["F"]).max()
+
+
+def test_n1_is_distinguishable_ring(oracle_lib):
+    from oracle import brute
+    R = gaussian_system(1, 7, seed=3)
+    beta, m = 1.4, 0.9
+    w = omega_p(7, beta)
+    k = 0.5 * m * w * w
+    o = oracle_lib.alg1(R, beta, m, w)
+    ring = R[0]
+    d = ring - np.roll(ring, -1, axis=0)
+    assert _rel(o["V"], k * (d * d).sum()) < 1e-14
+    Fring = -2 * k * ((ring - np.roll(ring, 1, axis=0)) + (ring - np.roll(ring, -1, axis=0)))
+    assert np.abs(o["F"][0] - Fring).max() < 1e-13 * np.abs(Fring).max()
+    assert o["Pr"][0, 0] == 1.0
+    assert np.abs(o["F"] - brute.perm_forces(R, (1,), k)).max() < 1e-12
+
+
+def test_n2_closed_form(oracle_lib):
+    from oracle import compositions
+    R = gaussian_system(2, 5, seed=4, sigma_c=0.4)
+    beta, m = 0.9, 1.0
+    w = omega_p(5, beta)
+    k = 0.5 * m * w * w
+    e11 = compositions.cycle_energy(R, 1, 1, k)
+    e22 = compositions.cycle_energy(R, 2, 2, k)
+    e12 = compositions.cycle_energy(R, 1, 2, k)
+    V = -math.log(0.5 * (math.exp(-beta * (e11 + e22)) + math.exp(-beta * e12))) / beta
+    o = oracle_lib.alg1(R, beta, m, w)
+    assert _rel(o["V"], V) < 1e-14
+    o2 = oracle_lib.alg1(R[::-1].copy(), beta, m, w)  # N=2 is symmetric under relabelling
+    assert _rel(o2["V"], V) < 1e-14
+
+
+@pytest.mark.parametrize("N", [1, 5, 37])
+def test_uniform_configuration_closed_forms(oracle_lib, N):
+    """All particles share one bead configuration: V = N E1 and
+    Pr[l->u] = 1/(l(l+1)) (u <= l < N), Pr[N->u] = 1/N, Pr[l->l+1] = l/(l+1)."""
+    P = 4
+    one = gaussian_system(1, P, seed=8, sigma_c=0.0, sigma_b=0.4)
+    R = np.repeat(one, N, axis=0)
+    beta, m = 1.0, 1.0
+    w = omega_p(P, beta)
+    k = 0.5 * m * w * w
+    d = one[0] - np.roll(one[0], -1, axis=0)
+    E1 = k * (d * d).sum()
+    o = oracle_lib.alg1(R, beta, m, w)
+    assert _rel(o["V"], N * E1) < 1e-13
+    want = np.zeros((N, N))
+    for l in range(1, N + 1):
+        for u in range(1, l + 1):
+            want[l - 1, u - 1] = 1.0 / N if l == N else 1.0 / (l * (l + 1))
+        if l < N:
+            want[l - 1, l] = l / (l + 1)
+    assert np.abs(o["Pr"] - want).max() < 1e-12
+    Fd = -2 * k * ((R - np.roll(R, 1, axis=1)) + (R - np.roll(R, -1, axis=1)))
+    assert np.abs(o["F"] - Fd).max() < 1e-12 * np.abs(Fd).max()
+
+
+def test_separated_limit(oracle_lib):
+    """Far-apart particles: V -> sum_l E^[l,l] + ln(N!)/beta, Pr -> identity."""
+    N, P = 9, 4
+    rng = np.random.default_rng(2)
+    cent = np.array([[40.0 * i, 0, 0] for i in range(N)])
+    R = cent[:, None, :] + rng.normal(0, 0.3, (N, P, 3))
+    beta, m = 1.0, 1.0
+    o = oracle_lib.alg1(R, beta, m, omega_p(P, beta))
+    Eself = np.diag(o["E"]).sum()
+    assert abs(o["V"] - (Eself + math.lgamma(N + 1) / beta)) < 1e-10
+    assert np.abs(o["Pr"] - np.eye(N)).max() < 1e-12
+
+
+def test_shift_choice_is_irrelevant(oracle_lib):
+    """Any stabilising shift is exact (appendix 'Numerical Stability')."""
+    R = cube_system(30, 3, seed=6, side=1.5)
+    w = omega_p(3, 1.0)
+    a = oracle_lib.alg1(R, 1.0, 1.0, w, shift_mode=0)
+    b = oracle_lib.alg1(R, 1.0, 1.0, w, shift_mode=1)
+    assert _rel(a["V"], b["V"]) < 1e-13
+    assert _fmax_rel(a["F"], b["F"]) < 1e-11
+
+
+def test_long_double_agrees_with_double(oracle_lib):
+    assert oracle_lib.long_double_mant_dig() >= 64
+    R = cube_system(128, 8, seed=7)
+    w = omega_p(8, 1.0)
+    a = oracle_lib.alg1(R, 1.0, 1.0, w, precision="f64")
+    b = oracle_lib.alg1(R, 1.0, 1.0, w, precision="f80")
+    assert _rel(a["V"], b["V"]) < 1e-13
+    assert _fmax_rel(a["F"], b["F"]) < 1e-10
+
+
+def test_relabelling(oracle_lib):
+    """V^[1,N] is not a symmetric function for N >= 3 (the paper notes it
+    differs from the sum over all permutations), while V_sym is.  Both are
+    compared against brute force on a 1D-embedded N=3, P=2 example."""
+    from oracle import brute
+    R = np.zeros((3, 2, 3))
+    R[0, :, 0] = [0.0, 0.5]
+    R[1, :, 0] = [1.0, 1.0]
+    R[2, :, 0] = [2.0, 2.0]
+    beta, m, w = 1.0, 1.0, math.sqrt(2.0)  # k = 1
+    perm = [0, 2, 1]
+    a = oracle_lib.alg1(R, beta, m, w)
+    b = oracle_lib.alg1(R[perm].copy(), beta, m, w)
+    ba = brute.exchange(R, beta, m, w)
+    bb = brute.exchange(R[perm].copy(), beta, m, w)
+    assert _rel(a["V"], ba["V"]) < 1e-14 and _rel(b["V"], bb["V"]) < 1e-14
+    assert abs(a["V"] - b["V"]) > 0.1
+    assert _rel(ba["Vsym"], bb["Vsym"]) < 1e-14
+
+
+def test_periodic_image_invariance(oracle_lib):
+    R = cube_system(20, 4, seed=13, side=3.0)
+    L = 3.0
+    w = omega_p(4, 1.0)
+    a = oracle_lib.alg1(R, 1.0, 1.0, w, L=L)
+    R2 = R.copy()
+    R2[5, 2, 1] += 2 * L
+    R2[7] += np.array([L, -L, 3 * L])
+    b = oracle_lib.alg1(R2, 1.0, 1.0, w, L=L)
+    assert _rel(a["V"], b["V"]) < 1e-12
+    assert _fmax_rel(a["F"], b["F"]) < 1e-11
+    big = oracle_lib.alg1(R, 1.0, 1.0, w, L=1e6)
+    op = oracle_lib.alg1(R, 1.0, 1.0, w)
+    assert _rel(big["V"], op["V"]) < 1e-12
