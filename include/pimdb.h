@@ -1,0 +1,232 @@
+/*
+ * pimdb -- bosonic path-integral MD exchange potential and forces on MI355X.
+ *
+ * C ABI of libpimdb.so.  The library evaluates, on one AMD gfx950 GPU, the
+ * bosonic ring-polymer potential V^[1,N] of Feldman & Hirshberg, "Quadratic
+ * Scaling Bosonic Path Integral Molecular Dynamics", and its force on every
+ * bead, for one system or for a batch of independent systems of uneven size.
+ *
+ * Definitions (paper, Sec. "Background: cubic scaling bosonic PIMD" and
+ * Sec. "Reducing the potential/force to O(N^2 + PN)"):
+ *   - N particles of mass m, P beads each, d = 3; bead j of particle l is r_l^j.
+ *   - k = (1/2) m omega_P^2.  omega_P is taken as given (the paper's choice
+ *     is sqrt(P)/(beta hbar)).
+ *   - E_int(l) = k sum_{j=1}^{P-1} |r_l^{j+1} - r_l^j|^2 (interior springs).
+ *   - E^[u,v] = energy of the ring formed by particles u..v: interior springs,
+ *     links from bead P of l to bead 1 of l+1, and the closing spring from
+ *     bead P of v to bead 1 of u.
+ *   - exp(-beta V^[1,v]) = (1/v) sum_{k=1}^{v} exp(-beta(V^[1,v-k] + E^[v-k+1,v])),
+ *     V^[1,0] = 0  (the forward recurrence; V^[1,N] is "the energy").
+ *   - forces = -grad V^[1,N] on all N*P beads: interior beads get the ordinary
+ *     ring-polymer force; beads 1 and P get the connection-probability-weighted
+ *     forces of Sec. "Force on exterior beads", with the probabilities of
+ *     Sec. "Connection probabilities" and Methods.
+ *   - Only the spring (kinetic) part is computed.  The interaction potential
+ *     U-bar of the paper is not included; an optional harmonic trap
+ *     (pimdb_set_trap) adds U-bar = (1/P) sum_j sum_l (1/2) m w^2 |r_l^j|^2.
+ *
+ * Data layout (all device pointers, FP64):
+ *   - Positions and forces are bead-major structure-of-arrays of shape
+ *     (P, 3, N): element (j, c, l) lives at index (j*3 + c)*N + l, with
+ *     0-based bead j (j = 0 is the paper's bead 1, j = P-1 is bead P),
+ *     component c and particle l.
+ *   - A batch of S systems is packed back to back: system s starts at element
+ *     offset pimdb_system_offset(h, s) = sum_{s'<s} 3 P_s' N_s'.
+ *   - Energies: one double per system.
+ *
+ * Ownership and execution:
+ *   - The caller owns every device buffer (positions, forces, energies,
+ *     workspace, adjoint state).  The library owns its handle and two small
+ *     device tables (system descriptors and the launch schedule) that it
+ *     allocates in pimdb_set_system / pimdb_set_batch and frees in
+ *     pimdb_destroy or on the next set call.
+ *   - Evaluation calls are asynchronous on the handle's stream, allocate
+ *     nothing, never synchronise the host and read no device value on the
+ *     host, so they may be captured into a HIP graph.  pimdb_status and
+ *     pimdb_debug_get are synchronous.
+ *   - Output buffers are overwritten, never accumulated.  Inputs and outputs
+ *     must not alias.  Calls on one handle must not overlap in time on
+ *     different streams (they share the workspace).
+ *
+ * Errors: every int-returning call returns PIMDB_OK (0) or a negative code;
+ * no exception crosses the ABI.  Errors found on the device (non-finite
+ * inputs or results, exponent range) cannot be returned by asynchronous
+ * calls; they set bits in a device status word read by pimdb_status.
+ */
+#ifndef PIMDB_H
+#define PIMDB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define PIMDB_OK 0
+#define PIMDB_EINVAL (-1)     /* bad argument: N < 1, P < 2, non-positive or non-finite beta/m/omega_P, L < 0, null pointer */
+#define PIMDB_ENOSYS (-2)     /* no system or batch has been set on the handle */
+#define PIMDB_EWORKSPACE (-3) /* no workspace bound, or the bound one is too small */
+#define PIMDB_EDEVICE (-4)    /* HIP runtime error (no device, launch failure); see pimdb_last_error */
+#define PIMDB_ENONFINITE (-5) /* returned by pimdb_status when the device status word is non-zero */
+#define PIMDB_ERANGE (-6)     /* size outside the supported range (N above PIMDB_MAX_N, batch too large) */
+
+/* ---- precision modes (pimdb_set_precision) ---- */
+#define PIMDB_FP64 0  /* every step in IEEE double */
+#define PIMDB_MIXED 1 /* endpoint-spring lengths |r_v^P - r_u^1|^2 in FP32 with compensated
+                         summation (displacements formed in FP64); recursions, probabilities
+                         and forces in FP64 */
+
+/* ---- device status bits (pimdb_status) ---- */
+#define PIMDB_STATUS_NONFINITE_INPUT 1  /* a position was NaN or infinite */
+#define PIMDB_STATUS_NONFINITE_OUTPUT 2 /* an energy or force came out NaN or infinite */
+#define PIMDB_STATUS_RANGE 4            /* a spring exponent beta*k*|d|^2 exceeded 2^29 in log2 units */
+
+/* ---- what pimdb_debug_get exports ---- */
+#define PIMDB_DEBUG_PROBABILITIES 1 /* dense N x N per system, [l-1][l'-1] = Pr[l -> l'] */
+#define PIMDB_DEBUG_CYCLE_ENERGIES 2 /* dense N x N per system, [u-1][v-1] = E^[u,v] for u <= v, 0 below */
+#define PIMDB_DEBUG_FORWARD 3        /* N+1 per system: V^[1,v], v = 0..N */
+#define PIMDB_DEBUG_BACKWARD 4       /* N+2 per system: index u holds V^[u,N] for u = 1..N+1; index 0 is 0 */
+
+#define PIMDB_MAX_N 4096
+#define PIMDB_MAX_BATCH 65536
+
+typedef struct pimdb_ctx *pimdb_t;
+
+/* Create a handle on HIP device `device` (the caller's current device is
+ * restored on return).  The handle starts on the null stream with no system,
+ * FP64 precision, open boundaries and no trap.  *out is set to NULL on
+ * failure.  Returns PIMDB_EDEVICE when the device cannot be used. */
+int pimdb_create(pimdb_t *out, int device);
+
+/* Free the handle and the tables it owns (waits for its stream first).
+ * NULL is accepted. */
+int pimdb_destroy(pimdb_t h);
+
+/* Stream (a hipStream_t passed as void*, NULL = null stream) on which every
+ * later evaluation is enqueued.  Used to follow the caller's current stream,
+ * e.g. during graph capture. */
+int pimdb_set_stream(pimdb_t h, void *stream);
+
+/* One system: N >= 1 particles, P >= 2 beads (the paper's exterior-bead
+ * formulas need distinct beads 1 and P), beta > 0, m > 0, omega_P > 0.
+ * Equivalent to pimdb_set_batch with S = 1.  Unbinds the workspace: query
+ * pimdb_workspace_bytes and bind again before evaluating. */
+int pimdb_set_system(pimdb_t h, int64_t N, int32_t P, double beta, double m, double omega_P);
+
+/* A batch of S independent systems, host arrays of length S.  Systems may
+ * differ in N, P, beta, m and omega_P.  One evaluation call processes the
+ * whole batch in a single kernel launch; the launch order puts the largest
+ * systems first.  Unbinds the workspace, as pimdb_set_system.  On error the
+ * handle is left with no system set. */
+int pimdb_set_batch(pimdb_t h, int32_t S, const int64_t *N, const int32_t *P, const double *beta,
+                    const double *m, const double *omega_P);
+
+/* Cubic periodic box of side L applied to every spring displacement as the
+ * minimum image d - L*rint(d/L) (round half to even).  L = 0 (default):
+ * open boundaries. */
+int pimdb_set_box(pimdb_t h, double L);
+
+/* Harmonic external trap of angular frequency w >= 0 (0 = none, default).
+ * When set, energies include (1/P) sum_{l,j} (1/2) m w^2 |r_l^j|^2 and forces
+ * include -(m w^2 / P) r_l^j on every bead (the paper's scaled potential
+ * U-bar for a harmonic trap). */
+int pimdb_set_trap(pimdb_t h, double w);
+
+/* PIMDB_FP64 (default) or PIMDB_MIXED. */
+int pimdb_set_precision(pimdb_t h, int mode);
+
+/* Launch shape override: threads per workgroup (64, 128, 256, 512 or 1024)
+ * and particles owned per thread in the recursions (1, 2, 4 or 8; 4 and 8 need
+ * threads <= 512).  Both 0
+ * restores the built-in choice.  PIMDB_EINVAL if the pair cannot hold the
+ * largest system (threads * per_thread < N_max).  With a system set, this
+ * unbinds the workspace like pimdb_set_batch. */
+int pimdb_set_tuning(pimdb_t h, int threads, int per_thread);
+
+/* Current launch shape (after the automatic choice). */
+int pimdb_get_tuning(pimdb_t h, int *threads, int *per_thread);
+
+/* Element offset of system s in packed position/force arrays; -1 if s is out
+ * of range or no system is set. */
+int64_t pimdb_system_offset(pimdb_t h, int32_t s);
+
+/* Total elements (sum 3 P_s N_s) of a packed position array; 0 if unset. */
+int64_t pimdb_total_elements(pimdb_t h);
+
+/* Device scratch bytes the evaluation calls need for the current batch. */
+size_t pimdb_workspace_bytes(pimdb_t h);
+
+/* Bind caller-owned device memory (at least pimdb_workspace_bytes, 256-byte
+ * aligned) as scratch.  The library clears its counters with a kernel on
+ * the handle's stream.  The memory must stay allocated while bound. */
+int pimdb_bind_workspace(pimdb_t h, void *dev_ptr, size_t bytes);
+
+/* V^[1,N] for every system -> energy[s].  Computes the interior spring
+ * energies and the forward recurrence only. */
+int pimdb_exchange_energy(pimdb_t h, const double *pos, double *energy);
+
+/* Energies (energy may be NULL) and forces -grad V^[1,N] (+ trap terms if set)
+ * on all beads of all systems.  This is the hot path: one kernel launch runs
+ * the interior springs, the forward and backward recursions of every system
+ * concurrently, and then the exterior-bead forces. */
+int pimdb_exchange_forces(pimdb_t h, const double *pos, double *forces, double *energy);
+
+/* Bytes of the adjoint state written by pimdb_exchange_energy_save. */
+size_t pimdb_state_bytes(pimdb_t h);
+
+/* Forward half for reverse-mode differentiation: energies -> energy[s], and
+ * the forward potentials plus the forward-weighted endpoint displacements
+ * -> state (caller-owned device buffer of pimdb_state_bytes). */
+int pimdb_exchange_energy_save(pimdb_t h, const double *pos, double *energy, void *state);
+
+/* Reverse half (the adjoint): grad_pos = grad_energy[s] * dV_s/dpos for every
+ * system s, from the positions and a state written by
+ * pimdb_exchange_energy_save on the same positions.  grad_energy is a device
+ * array of S doubles.  This runs the backward recursion and the
+ * connection-probability force evaluation of the paper. */
+int pimdb_exchange_adjoint(pimdb_t h, const double *pos, const void *state, const double *grad_energy,
+                           double *grad_pos);
+
+/* Velocity-Verlet step for every bead of every system (mass m_s per bead):
+ *   vel += dt/(2 m) forces; pos += dt vel; forces, energy <- pimdb_exchange_forces(pos);
+ *   vel += dt/(2 m) forces.
+ * forces must hold the forces of the incoming positions.  Asynchronous and
+ * graph-capturable like pimdb_exchange_forces.  energy may be NULL. */
+int pimdb_md_step(pimdb_t h, double *pos, double *vel, double *forces, double *energy, double dt);
+
+/* Forces and energies of distinguishable particles (each particle its own
+ * closed ring; no exchange) with the same layout and trap/box settings; the
+ * reference cost the paper compares bosonic PIMD with. */
+int pimdb_distinguishable_forces(pimdb_t h, const double *pos, double *forces, double *energy);
+
+/* Synchronous export of intermediates for system s (see PIMDB_DEBUG_*) into
+ * device memory dst, recomputed from pos.  For tests and analysis; allocates
+ * nothing but synchronises the stream. */
+int pimdb_debug_get(pimdb_t h, const double *pos, int32_t s, int what, double *dst);
+
+/* Endpoint springs s(v,u) = k |r_v^P - r_u^1|^2 of system s, packed lower
+ * triangle row by row (row v = 1..N holds u = 1..v; entry (v,u) at index
+ * v(v-1)/2 + u-1), FP64 (as_float = 0) or FP32 (as_float = 1, compensated),
+ * into device memory dst.  Asynchronous.  This is the pairwise part the
+ * exchange kernels evaluate in registers without storing it. */
+int pimdb_endpoint_springs(pimdb_t h, const double *pos, int32_t s, int as_float, void *dst);
+
+/* Synchronise the stream, read and clear the device status word.  *flags
+ * (may be NULL) receives the PIMDB_STATUS_* bits.  Returns PIMDB_ENONFINITE
+ * if any bit was set, PIMDB_OK otherwise. */
+int pimdb_status(pimdb_t h, int32_t *flags);
+
+/* Static text for a return code. */
+const char *pimdb_strerror(int code);
+
+/* Text of the last error recorded on the handle (HIP error string or the
+ * argument that was rejected); "" if none.  Valid until the next call. */
+const char *pimdb_last_error(pimdb_t h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIMDB_H */

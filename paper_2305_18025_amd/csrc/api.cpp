@@ -1,0 +1,547 @@
+// Host side of the C ABI declared in include/pimdb.h: handle, argument
+// validation, batch schedule, workspace accounting and kernel launches.
+#include "../../include/pimdb.h"
+#include "internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+using namespace pimdb;
+
+namespace pimdb {
+size_t exchange_smem_bytes(int threads);
+}
+
+struct pimdb_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    // batch definition
+    int S = 0;
+    std::vector<int64_t> N;
+    std::vector<int32_t> P;
+    std::vector<double> beta, m, omegaP;
+    int64_t Nmax = 0;
+    // derived tables (host copies and device copies)
+    std::vector<SysDesc> desc;
+    int64_t total_elems = 0;
+    int64_t ws_doubles = 0; // after header and counters
+    int64_t st_doubles = 0;
+    SysDesc *d_desc = nullptr;
+    Item *d_items = nullptr; // [fb | f | b | s] item lists back to back
+    int n_fb = 0, n_f = 0, n_b = 0, n_s = 0;
+    EChunk *d_echunks = nullptr;
+    int n_echunks = 0;
+    // settings
+    double box = 0.0, trap_w = 0.0;
+    int precision = PIMDB_FP64;
+    int user_threads = 0, user_per = 0;
+    int threads = 256, per_thread = 4;
+    // workspace
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    std::string last_error;
+};
+
+namespace {
+
+int fail(pimdb_t h, int code, const std::string &msg) {
+    if (h) h->last_error = msg;
+    return code;
+}
+
+int hip_fail(pimdb_t h, hipError_t e, const char *where) {
+    return fail(h, PIMDB_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+struct DeviceGuard {
+    int old = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&old) != hipSuccess) old = -1;
+        if (old != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (old >= 0 && hipGetDevice(&cur) == hipSuccess && cur != old) (void)hipSetDevice(old);
+    }
+};
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+bool pow2_threads(int t) { return t == 64 || t == 128 || t == 256 || t == 512 || t == 1024; }
+
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+int64_t counters_bytes(int S) { return round_up((int64_t)S * 4, 256); }
+
+// Automatic launch shape: 2 particles per thread in the recursions and the
+// smallest power-of-two workgroup that holds the largest system; above 2048
+// particles, 8 per thread in 512-thread workgroups.
+void auto_tuning(int64_t Nmax, int &threads, int &per) {
+    if (Nmax > 2048) {
+        threads = 512;
+        per = 8;
+        return;
+    }
+    per = 2;
+    int64_t t = 64;
+    while (t * per < Nmax) t *= 2;
+    threads = (int)t;
+}
+
+void free_tables(pimdb_t h) {
+    if (h->d_desc) (void)hipFree(h->d_desc);
+    if (h->d_items) (void)hipFree(h->d_items);
+    if (h->d_echunks) (void)hipFree(h->d_echunks);
+    h->d_desc = nullptr;
+    h->d_items = nullptr;
+    h->d_echunks = nullptr;
+    h->n_fb = h->n_f = h->n_b = h->n_s = h->n_echunks = 0;
+}
+
+// Build descriptors, the launch schedule (largest systems first) and the MD
+// element chunks for the current batch and launch shape; upload them.
+int build_tables(pimdb_t h) {
+    // the workspace layout (counters, per-system regions) depends on the
+    // batch and the launch shape: the caller binds a workspace again
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, PIMDB_EDEVICE, "cannot select device");
+    if (h->user_threads) {
+        h->threads = h->user_threads;
+        h->per_thread = h->user_per;
+    } else {
+        auto_tuning(h->Nmax, h->threads, h->per_thread);
+    }
+    const int T = h->threads;
+    const int S = h->S;
+    h->desc.assign(S, SysDesc{});
+    int64_t off = 0, ws = 0, st = 0;
+    for (int s = 0; s < S; ++s) {
+        SysDesc &d = h->desc[s];
+        d.off = off;
+        d.ws = ws;
+        d.st = st;
+        d.N = (int32_t)h->N[s];
+        d.P = h->P[s];
+        d.nchunk = (int32_t)((h->N[s] + T - 1) / T);
+        d.beta = h->beta[s];
+        d.m = h->m[s];
+        d.omegaP = h->omegaP[s];
+        d.k = 0.5 * d.m * d.omegaP * d.omegaP;
+        d.mw2 = d.m * d.omegaP * d.omegaP;
+        d.kappa = -d.beta * d.k * 1.4426950408889634; // log2(e)
+        off += (int64_t)3 * d.P * d.N;
+        ws += round_up(WsLayout::total(d.N, d.nchunk), 32);
+        st += round_up(StLayout::total(d.N), 32);
+    }
+    h->total_elems = off;
+    h->ws_doubles = ws;
+    h->st_doubles = st;
+
+    // schedule: recursion items by decreasing N (forward and backward of a
+    // system adjacent), then the spring items.
+    std::vector<int> order(S);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return h->N[a] > h->N[b]; });
+    std::vector<Item> fb, f, b, sp;
+    for (int s : order) {
+        fb.push_back(Item{s, ROLE_FORWARD, 0, 0});
+        fb.push_back(Item{s, ROLE_BACKWARD, 0, 0});
+        f.push_back(Item{s, ROLE_FORWARD, 0, 0});
+        b.push_back(Item{s, ROLE_BACKWARD, 0, 0});
+    }
+    for (int s : order)
+        for (int c = 0; c < h->desc[s].nchunk; ++c) sp.push_back(Item{s, ROLE_SPRINGS, c, 0});
+    std::vector<Item> all;
+    all.insert(all.end(), fb.begin(), fb.end());
+    all.insert(all.end(), sp.begin(), sp.end());
+    all.insert(all.end(), f.begin(), f.end());
+    all.insert(all.end(), sp.begin(), sp.end());
+    all.insert(all.end(), b.begin(), b.end());
+    all.insert(all.end(), sp.begin(), sp.end());
+    all.insert(all.end(), sp.begin(), sp.end());
+    h->n_fb = (int)(fb.size() + sp.size());
+    h->n_f = (int)(f.size() + sp.size());
+    h->n_b = (int)(b.size() + sp.size());
+    h->n_s = (int)sp.size();
+
+    std::vector<EChunk> ec;
+    const int64_t CE = 1 << 16;
+    for (int s = 0; s < S; ++s) {
+        const int64_t b0 = h->desc[s].off, e0 = b0 + (int64_t)3 * h->desc[s].P * h->desc[s].N;
+        for (int64_t x = b0; x < e0; x += CE) ec.push_back(EChunk{s, 0, x, std::min(e0, x + CE)});
+    }
+
+    free_tables(h);
+    h->n_fb = (int)(fb.size() + sp.size());
+    h->n_f = (int)(f.size() + sp.size());
+    h->n_b = (int)(b.size() + sp.size());
+    h->n_s = (int)sp.size();
+    h->n_echunks = (int)ec.size();
+    hipError_t e;
+    if ((e = hipMalloc(&h->d_desc, sizeof(SysDesc) * S)) != hipSuccess) return hip_fail(h, e, "hipMalloc");
+    if ((e = hipMalloc(&h->d_items, sizeof(Item) * all.size())) != hipSuccess) return hip_fail(h, e, "hipMalloc");
+    if ((e = hipMalloc(&h->d_echunks, sizeof(EChunk) * ec.size())) != hipSuccess) return hip_fail(h, e, "hipMalloc");
+    if ((e = hipMemcpy(h->d_desc, h->desc.data(), sizeof(SysDesc) * S, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(h, e, "hipMemcpy");
+    if ((e = hipMemcpy(h->d_items, all.data(), sizeof(Item) * all.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(h, e, "hipMemcpy");
+    if ((e = hipMemcpy(h->d_echunks, ec.data(), sizeof(EChunk) * ec.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(h, e, "hipMemcpy");
+    return PIMDB_OK;
+}
+
+size_t ws_bytes_needed(pimdb_t h) {
+    return (size_t)(WS_HEADER_BYTES + counters_bytes(h->S) + h->ws_doubles * 8);
+}
+
+int check_ready(pimdb_t h) {
+    if (!h) return PIMDB_EINVAL;
+    if (h->S <= 0) return fail(h, PIMDB_ENOSYS, "no system set");
+    if (!h->ws || h->ws_bytes < ws_bytes_needed(h))
+        return fail(h, PIMDB_EWORKSPACE, "workspace not bound or too small");
+    return PIMDB_OK;
+}
+
+LaunchArgs base_args(pimdb_t h) {
+    LaunchArgs a{};
+    a.sys = h->d_desc;
+    a.flags = (int32_t *)h->ws;
+    a.counters = (int32_t *)(h->ws + WS_HEADER_BYTES);
+    a.ws = (double *)(h->ws + WS_HEADER_BYTES + counters_bytes(h->S));
+    a.box = h->box;
+    a.inv_box = h->box > 0 ? 1.0 / h->box : 0.0;
+    a.trap_w2 = h->trap_w * h->trap_w;
+    a.mixed = h->precision == PIMDB_MIXED;
+    return a;
+}
+
+// Item list ranges inside d_items (see build_tables).
+const Item *items_fb(pimdb_t h) { return h->d_items; }
+const Item *items_f(pimdb_t h) { return h->d_items + h->n_fb; }
+const Item *items_b(pimdb_t h) { return h->d_items + h->n_fb + h->n_f; }
+const Item *items_s(pimdb_t h) { return h->d_items + h->n_fb + h->n_f + h->n_b; }
+
+int run(pimdb_t h, LaunchArgs &a, const Item *items, int n) {
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, PIMDB_EDEVICE, "cannot select device");
+    a.items = items;
+    hipError_t e = launch_exchange(a, n, h->threads, h->per_thread, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "exchange launch");
+    return PIMDB_OK;
+}
+
+int set_batch_impl(pimdb_t h, int32_t S, const int64_t *N, const int32_t *P, const double *beta,
+                   const double *m, const double *omega_P) {
+    if (!h) return PIMDB_EINVAL;
+    if (S < 1 || !N || !P || !beta || !m || !omega_P) return fail(h, PIMDB_EINVAL, "bad batch arguments");
+    if (S > PIMDB_MAX_BATCH) return fail(h, PIMDB_ERANGE, "batch too large");
+    int64_t nmax = 0;
+    for (int s = 0; s < S; ++s) {
+        if (N[s] < 1) return fail(h, PIMDB_EINVAL, "N < 1");
+        if (P[s] < 2) return fail(h, PIMDB_EINVAL, "P < 2");
+        if (!finite_pos(beta[s]) || !finite_pos(m[s]) || !finite_pos(omega_P[s]))
+            return fail(h, PIMDB_EINVAL, "beta, m and omega_P must be finite and positive");
+        if (N[s] > PIMDB_MAX_N) return fail(h, PIMDB_ERANGE, "N above PIMDB_MAX_N");
+        nmax = std::max<int64_t>(nmax, N[s]);
+    }
+    if (h->user_threads && (int64_t)h->user_threads * h->user_per < nmax)
+        return fail(h, PIMDB_EINVAL, "tuning override too small for this batch");
+    h->S = S;
+    h->N.assign(N, N + S);
+    h->P.assign(P, P + S);
+    h->beta.assign(beta, beta + S);
+    h->m.assign(m, m + S);
+    h->omegaP.assign(omega_P, omega_P + S);
+    h->Nmax = nmax;
+    const int rc = build_tables(h);
+    if (rc != PIMDB_OK) h->S = 0;
+    return rc;
+}
+
+} // namespace
+
+extern "C" {
+
+int pimdb_create(pimdb_t *out, int device) {
+    if (!out) return PIMDB_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return PIMDB_EDEVICE;
+    if (device < 0 || device >= count) return PIMDB_EINVAL;
+    pimdb_t h = new (std::nothrow) pimdb_ctx();
+    if (!h) return PIMDB_EDEVICE;
+    h->device = device;
+    {
+        DeviceGuard g(device);
+        if (!g.ok) {
+            delete h;
+            return PIMDB_EDEVICE;
+        }
+    }
+    *out = h;
+    return PIMDB_OK;
+}
+
+int pimdb_destroy(pimdb_t h) {
+    if (!h) return PIMDB_OK;
+    {
+        DeviceGuard g(h->device);
+        (void)hipStreamSynchronize(h->stream);
+        free_tables(h);
+    }
+    delete h;
+    return PIMDB_OK;
+}
+
+int pimdb_set_stream(pimdb_t h, void *stream) {
+    if (!h) return PIMDB_EINVAL;
+    h->stream = (hipStream_t)stream;
+    return PIMDB_OK;
+}
+
+int pimdb_set_system(pimdb_t h, int64_t N, int32_t P, double beta, double m, double omega_P) {
+    return set_batch_impl(h, 1, &N, &P, &beta, &m, &omega_P);
+}
+
+int pimdb_set_batch(pimdb_t h, int32_t S, const int64_t *N, const int32_t *P, const double *beta,
+                    const double *m, const double *omega_P) {
+    return set_batch_impl(h, S, N, P, beta, m, omega_P);
+}
+
+int pimdb_set_box(pimdb_t h, double L) {
+    if (!h) return PIMDB_EINVAL;
+    if (!std::isfinite(L) || L < 0) return fail(h, PIMDB_EINVAL, "box side must be finite and >= 0");
+    h->box = L;
+    return PIMDB_OK;
+}
+
+int pimdb_set_trap(pimdb_t h, double w) {
+    if (!h) return PIMDB_EINVAL;
+    if (!std::isfinite(w) || w < 0) return fail(h, PIMDB_EINVAL, "trap frequency must be finite and >= 0");
+    h->trap_w = w;
+    return PIMDB_OK;
+}
+
+int pimdb_set_precision(pimdb_t h, int mode) {
+    if (!h) return PIMDB_EINVAL;
+    if (mode != PIMDB_FP64 && mode != PIMDB_MIXED) return fail(h, PIMDB_EINVAL, "unknown precision mode");
+    h->precision = mode;
+    return PIMDB_OK;
+}
+
+int pimdb_set_tuning(pimdb_t h, int threads, int per_thread) {
+    if (!h) return PIMDB_EINVAL;
+    if (threads == 0 && per_thread == 0) {
+        h->user_threads = h->user_per = 0;
+    } else {
+        if (!pow2_threads(threads)) return fail(h, PIMDB_EINVAL, "threads must be 64, 128, 256, 512 or 1024");
+        if (per_thread != 1 && per_thread != 2 && per_thread != 4 && per_thread != 8)
+            return fail(h, PIMDB_EINVAL, "per_thread must be 1, 2, 4 or 8");
+        if (per_thread >= 4 && threads > 512) return fail(h, PIMDB_EINVAL, "per_thread 4 and 8 need threads <= 512");
+        if (h->S > 0 && (int64_t)threads * per_thread < h->Nmax)
+            return fail(h, PIMDB_EINVAL, "threads * per_thread below the largest N");
+        h->user_threads = threads;
+        h->user_per = per_thread;
+    }
+    if (h->S > 0) return build_tables(h);
+    return PIMDB_OK;
+}
+
+int pimdb_get_tuning(pimdb_t h, int *threads, int *per_thread) {
+    if (!h || !threads || !per_thread) return PIMDB_EINVAL;
+    *threads = h->threads;
+    *per_thread = h->per_thread;
+    return PIMDB_OK;
+}
+
+int64_t pimdb_system_offset(pimdb_t h, int32_t s) {
+    if (!h || s < 0 || s >= h->S) return -1;
+    return h->desc[s].off;
+}
+
+int64_t pimdb_total_elements(pimdb_t h) { return h ? h->total_elems : 0; }
+
+size_t pimdb_workspace_bytes(pimdb_t h) {
+    if (!h || h->S <= 0) return 0;
+    return ws_bytes_needed(h);
+}
+
+size_t pimdb_state_bytes(pimdb_t h) {
+    if (!h || h->S <= 0) return 0;
+    return (size_t)h->st_doubles * 8;
+}
+
+int pimdb_bind_workspace(pimdb_t h, void *dev_ptr, size_t bytes) {
+    if (!h) return PIMDB_EINVAL;
+    if (!dev_ptr) return fail(h, PIMDB_EINVAL, "null workspace");
+    if (((uintptr_t)dev_ptr) % 256) return fail(h, PIMDB_EINVAL, "workspace must be 256-byte aligned");
+    if (h->S > 0 && bytes < ws_bytes_needed(h)) return fail(h, PIMDB_EWORKSPACE, "workspace too small");
+    h->ws = (char *)dev_ptr;
+    h->ws_bytes = bytes;
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, PIMDB_EDEVICE, "cannot select device");
+    const int64_t nints = (WS_HEADER_BYTES + counters_bytes(h->S > 0 ? h->S : 1)) / 4;
+    const int64_t lim = (int64_t)bytes / 4;
+    hipError_t e = launch_clear((int32_t *)dev_ptr, std::min(nints, lim), h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "clear workspace");
+    return PIMDB_OK;
+}
+
+int pimdb_exchange_energy(pimdb_t h, const double *pos, double *energy) {
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (!pos || !energy) return fail(h, PIMDB_EINVAL, "null pointer");
+    LaunchArgs a = base_args(h);
+    a.pos = pos;
+    a.energy = energy;
+    a.mode = M_FWD | M_ENERGY;
+    return run(h, a, items_f(h), h->n_f);
+}
+
+int pimdb_exchange_forces(pimdb_t h, const double *pos, double *forces, double *energy) {
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (!pos || !forces) return fail(h, PIMDB_EINVAL, "null pointer");
+    if (pos == forces) return fail(h, PIMDB_EINVAL, "positions and forces alias");
+    LaunchArgs a = base_args(h);
+    a.pos = pos;
+    a.out = forces;
+    a.energy = energy;
+    a.mode = M_FWD | M_BWD | M_WSUM | M_FORCES | (energy ? M_ENERGY : 0);
+    return run(h, a, items_fb(h), h->n_fb);
+}
+
+int pimdb_exchange_energy_save(pimdb_t h, const double *pos, double *energy, void *state) {
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (!pos || !energy || !state) return fail(h, PIMDB_EINVAL, "null pointer");
+    LaunchArgs a = base_args(h);
+    a.pos = pos;
+    a.energy = energy;
+    a.state = (double *)state;
+    a.mode = M_FWD | M_WSUM | M_SAVE | M_ENERGY;
+    return run(h, a, items_f(h), h->n_f);
+}
+
+int pimdb_exchange_adjoint(pimdb_t h, const double *pos, const void *state, const double *grad_energy,
+                           double *grad_pos) {
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (!pos || !state || !grad_energy || !grad_pos) return fail(h, PIMDB_EINVAL, "null pointer");
+    if (pos == grad_pos) return fail(h, PIMDB_EINVAL, "positions and gradient alias");
+    LaunchArgs a = base_args(h);
+    a.pos = pos;
+    a.out = grad_pos;
+    a.state = (double *)state;
+    a.gscale = grad_energy;
+    a.mode = M_BWD | M_FORCES | M_ADJOINT;
+    return run(h, a, items_b(h), h->n_b);
+}
+
+int pimdb_md_step(pimdb_t h, double *pos, double *vel, double *forces, double *energy, double dt) {
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (!pos || !vel || !forces) return fail(h, PIMDB_EINVAL, "null pointer");
+    if (!std::isfinite(dt)) return fail(h, PIMDB_EINVAL, "dt must be finite");
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, PIMDB_EDEVICE, "cannot select device");
+    hipError_t e = launch_md_update(h->d_desc, h->d_echunks, h->n_echunks, pos, vel, forces, dt, 1, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "md kick/drift");
+    rc = pimdb_exchange_forces(h, pos, forces, energy);
+    if (rc) return rc;
+    e = launch_md_update(h->d_desc, h->d_echunks, h->n_echunks, pos, vel, forces, dt, 0, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "md kick");
+    return PIMDB_OK;
+}
+
+int pimdb_distinguishable_forces(pimdb_t h, const double *pos, double *forces, double *energy) {
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (!pos || !forces) return fail(h, PIMDB_EINVAL, "null pointer");
+    if (pos == forces) return fail(h, PIMDB_EINVAL, "positions and forces alias");
+    LaunchArgs a = base_args(h);
+    a.pos = pos;
+    a.out = forces;
+    a.energy = energy;
+    a.mode = M_DIST | M_FORCES | (energy ? M_ENERGY : 0);
+    return run(h, a, items_s(h), h->n_s);
+}
+
+int pimdb_debug_get(pimdb_t h, const double *pos, int32_t s, int what, double *dst) {
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (!pos || !dst) return fail(h, PIMDB_EINVAL, "null pointer");
+    if (s < 0 || s >= h->S) return fail(h, PIMDB_EINVAL, "system index out of range");
+    if (what < PIMDB_DEBUG_PROBABILITIES || what > PIMDB_DEBUG_BACKWARD)
+        return fail(h, PIMDB_EINVAL, "unknown debug export");
+    // recursions of the whole batch without force output
+    LaunchArgs a = base_args(h);
+    a.pos = pos;
+    a.mode = M_FWD | M_BWD | M_WSUM;
+    if ((rc = run(h, a, items_fb(h), h->n_fb))) return rc;
+    DeviceGuard g(h->device);
+    hipError_t e;
+    if (what != PIMDB_DEBUG_PROBABILITIES) {
+        if ((e = launch_debug_prefix(a, s, h->threads, h->stream)) != hipSuccess)
+            return hip_fail(h, e, "debug prefix");
+    }
+    if ((e = launch_debug_table(a, s, (int)h->N[s], what, dst, h->stream)) != hipSuccess)
+        return hip_fail(h, e, "debug table");
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(h, e, "synchronize");
+    return PIMDB_OK;
+}
+
+int pimdb_endpoint_springs(pimdb_t h, const double *pos, int32_t s, int as_float, void *dst) {
+    if (!h) return PIMDB_EINVAL;
+    if (h->S <= 0) return fail(h, PIMDB_ENOSYS, "no system set");
+    if (!pos || !dst) return fail(h, PIMDB_EINVAL, "null pointer");
+    if (s < 0 || s >= h->S) return fail(h, PIMDB_EINVAL, "system index out of range");
+    LaunchArgs a = base_args(h);
+    a.pos = pos;
+    DeviceGuard g(h->device);
+    hipError_t e = launch_endpoint_springs(a, s, (int)h->N[s], as_float ? 1 : 0, dst, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "endpoint springs");
+    return PIMDB_OK;
+}
+
+int pimdb_status(pimdb_t h, int32_t *flags) {
+    if (!h) return PIMDB_EINVAL;
+    if (!h->ws) return fail(h, PIMDB_EWORKSPACE, "workspace not bound");
+    DeviceGuard g(h->device);
+    hipError_t e;
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(h, e, "synchronize");
+    int32_t v = 0;
+    if ((e = hipMemcpy(&v, h->ws, sizeof(v), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(h, e, "read status");
+    if ((e = launch_clear((int32_t *)h->ws, 1, h->stream)) != hipSuccess) return hip_fail(h, e, "clear status");
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(h, e, "synchronize");
+    if (flags) *flags = v;
+    return v ? PIMDB_ENONFINITE : PIMDB_OK;
+}
+
+const char *pimdb_strerror(int code) {
+    switch (code) {
+    case PIMDB_OK: return "success";
+    case PIMDB_EINVAL: return "invalid argument";
+    case PIMDB_ENOSYS: return "no system set";
+    case PIMDB_EWORKSPACE: return "workspace missing or too small";
+    case PIMDB_EDEVICE: return "HIP device error";
+    case PIMDB_ENONFINITE: return "non-finite input or result (device status set)";
+    case PIMDB_ERANGE: return "size out of supported range";
+    default: return "unknown error";
+    }
+}
+
+const char *pimdb_last_error(pimdb_t h) { return h ? h->last_error.c_str() : ""; }
+
+} // extern "C"

@@ -1,0 +1,115 @@
+// Internal types shared by the host API (api.cpp) and the kernels
+// (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pimdb {
+
+// Roles of a workgroup in the fused evaluation launch.
+enum Role : int32_t {
+    ROLE_FORWARD = 0,  // forward recursion of one system
+    ROLE_BACKWARD = 1, // backward recursion of one system
+    ROLE_SPRINGS = 2,  // interior springs of one block of particles
+};
+
+// Evaluation modes (bit set).
+enum ModeBits : int32_t {
+    M_FWD = 1,        // run forward recursions
+    M_BWD = 2,        // run backward recursions
+    M_WSUM = 4,       // forward recursion accumulates weighted displacements
+    M_FORCES = 8,     // write forces (interior by springs, exterior by finalize)
+    M_ENERGY = 16,    // write energies
+    M_ADJOINT = 32,   // forces scaled by -grad_energy[s]; forward results read from state
+    M_SAVE = 64,      // forward results written to state instead of the workspace
+    M_DIST = 128,     // distinguishable particles: springs close each ring, no recursions
+};
+
+// Per-system descriptor (device table, built by pimdb_set_batch).
+struct SysDesc {
+    int64_t off;    // element offset of the system in packed (P,3,N) arrays
+    int64_t ws;     // offset in doubles of the system's region in the workspace
+    int64_t st;     // offset in doubles of the system's region in the adjoint state
+    int32_t N, P;
+    int32_t nchunk; // number of ROLE_SPRINGS items (ceil(N / threads))
+    int32_t pad;
+    double beta, m, omegaP;
+    double k;       // (1/2) m omega_P^2
+    double mw2;     // m omega_P^2
+    double kappa;   // -beta k log2(e): spring exponent factor in log2 units
+};
+
+// One workgroup's job.
+struct Item {
+    int32_t sys;
+    int32_t role;
+    int32_t idx; // chunk index for ROLE_SPRINGS
+    int32_t pad;
+};
+
+// Per-system workspace layout, offsets in doubles from SysDesc::ws.
+//   zf_m[N+1], zf_e[N+1] : forward  Z_f[v] = zf_m * 2^zf_e, v = 0..N
+//   zb_m[N+2], zb_e[N+2] : backward Z_b[u] = zb_m * 2^zb_e, u = 1..N+1
+//   rf[3][N]             : forward-weighted mean endpoint displacement
+//   rb[3][N]             : backward-weighted mean endpoint displacement
+//   epart[nchunk]        : interior/trap energy partial sums
+//   cpre[N+1]            : gauge prefix sums (debug exports only)
+struct WsLayout {
+    static __host__ __device__ inline int64_t zf_m(int N) { return 0; }
+    static __host__ __device__ inline int64_t zf_e(int N) { return (int64_t)N + 1; }
+    static __host__ __device__ inline int64_t zb_m(int N) { return 2 * ((int64_t)N + 1); }
+    static __host__ __device__ inline int64_t zb_e(int N) { return 2 * ((int64_t)N + 1) + (N + 2); }
+    static __host__ __device__ inline int64_t rf(int N) { return 2 * ((int64_t)N + 1) + 2 * ((int64_t)N + 2); }
+    static __host__ __device__ inline int64_t rb(int N) { return rf(N) + 3 * (int64_t)N; }
+    static __host__ __device__ inline int64_t epart(int N) { return rb(N) + 3 * (int64_t)N; }
+    static __host__ __device__ inline int64_t cpre(int N, int nchunk) { return epart(N) + nchunk; }
+    static __host__ __device__ inline int64_t total(int N, int nchunk) { return cpre(N, nchunk) + N + 1; }
+};
+
+// Adjoint state layout per system, offsets in doubles from SysDesc::st:
+//   zf_m[N+1], zf_e[N+1], rf[3][N]
+struct StLayout {
+    static __host__ __device__ inline int64_t zf_m(int N) { return 0; }
+    static __host__ __device__ inline int64_t zf_e(int N) { return (int64_t)N + 1; }
+    static __host__ __device__ inline int64_t rf(int N) { return 2 * ((int64_t)N + 1); }
+    static __host__ __device__ inline int64_t total(int N) { return 2 * ((int64_t)N + 1) + 3 * (int64_t)N; }
+};
+
+// Workspace header (bytes): status word, then one arrival counter per system.
+constexpr int64_t WS_HEADER_BYTES = 256;
+
+struct LaunchArgs {
+    const SysDesc *sys;
+    const Item *items;
+    const double *pos;
+    double *out;           // forces / gradient (may be null: no force writes)
+    double *energy;        // per-system energies (may be null)
+    double *ws;            // workspace doubles (after the header and counters)
+    int32_t *counters;     // per-system arrival counters
+    int32_t *flags;        // status word
+    double *state;         // adjoint state (M_SAVE writes it, M_ADJOINT reads it)
+    const double *gscale;  // adjoint: grad of energy per system
+    double box, inv_box;   // periodic box (0 = open)
+    double trap_w2;        // trap omega^2 (0 = none)
+    int32_t mode;
+    int32_t mixed;         // 1: FP32 compensated endpoint spring lengths
+};
+
+// Kernel launch entry points (kernels.hip).
+hipError_t launch_exchange(const LaunchArgs &a, int nitems, int threads, int per_thread, hipStream_t st);
+hipError_t launch_clear(int32_t *p, int64_t n, hipStream_t st);
+// Element range of one system handled by one workgroup of the MD kernels.
+struct EChunk {
+    int32_t sys;
+    int32_t pad;
+    int64_t begin, end; // element range in packed arrays
+};
+
+hipError_t launch_md_update(const SysDesc *sys, const EChunk *chunks, int nchunks, double *pos,
+                            double *vel, const double *forces, double dt, int drift, hipStream_t st);
+hipError_t launch_debug_prefix(const LaunchArgs &a, int s, int threads, hipStream_t st);
+hipError_t launch_debug_table(const LaunchArgs &a, int s, int N, int what, double *dst, hipStream_t st);
+hipError_t launch_endpoint_springs(const LaunchArgs &a, int s, int N, int as_float, void *dst, hipStream_t st);
+
+} // namespace pimdb
