@@ -81,16 +81,19 @@ int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 int64_t counters_bytes(int S) { return round_up((int64_t)S * 4, 256); }
 
-// Automatic launch shape: 2 particles per thread in the recursions and the
-// smallest power-of-two workgroup that holds the largest system; above 2048
-// particles, 8 per thread in 512-thread workgroups.
-void auto_tuning(int64_t Nmax, int &threads, int &per) {
+// Automatic launch shape.  One system: latency first -- the widest
+// workgroup (most waves to hide FP64 latency) holding the system with 1 or 2
+// particles per thread.  Several systems: throughput first -- 4 particles per
+// thread (more independent accumulators per lane) in the smallest workgroup
+// that holds the largest system.  Above 2048 particles: 8 per thread in
+// 512-thread workgroups (register budget).
+void auto_tuning(int64_t Nmax, int S, int &threads, int &per) {
     if (Nmax > 2048) {
         threads = 512;
         per = 8;
         return;
     }
-    per = 2;
+    per = S == 1 ? (Nmax > 1024 ? 2 : 1) : 4;
     int64_t t = 64;
     while (t * per < Nmax) t *= 2;
     threads = (int)t;
@@ -119,7 +122,7 @@ int build_tables(pimdb_t h) {
         h->threads = h->user_threads;
         h->per_thread = h->user_per;
     } else {
-        auto_tuning(h->Nmax, h->threads, h->per_thread);
+        auto_tuning(h->Nmax, h->S, h->threads, h->per_thread);
     }
     const int T = h->threads;
     const int S = h->S;

@@ -60,21 +60,20 @@ constexpr int EMIN = -(1 << 30);         // exponent of an empty accumulator
 
 enum StatusBits { ST_NONFINITE_IN = 1, ST_NONFINITE_OUT = 2, ST_RANGE = 4 };
 
-// 2^f for |f| <= 1/2: degree-13 Taylor polynomial of e^(f ln 2)
-// (coefficients (ln 2)^k / k!, highest degree first, generated by
-// gen_exp2_coeffs.py).  Kept in constant memory so the wave-uniform
-// coefficients live in scalar registers and every Horner step is one
-// v_fma_f64.
-__constant__ double EXP2_C[14] = {
-    1.3691488853904128e-12, 2.5678435993488206e-11, 4.4455382718708116e-10, 7.054911620801123e-09,
-    1.01780860092397e-07,   1.321548679014431e-06,  1.5252733804059841e-05, 0.0001540353039338161,
-    0.0013333558146428443,  0.009618129107628477,   0.05550410866482158,    0.24022650695910072,
-    0.6931471805599453,     1.0};
+// 2^f for |f| <= 1/2: degree-11 minimax polynomial (relative approximation
+// error 3e-18, below the rounding of its evaluation; coefficients from
+// gen_exp2_coeffs.py), highest degree first.  Kept in constant memory so the
+// wave-uniform coefficients live in scalar registers and every Horner step
+// is one v_fma_f64.
+__constant__ double EXP2_C[12] = {
+    4.4352809446103363e-10, 7.074105626245659e-09, 1.0178198033328528e-07, 1.321543308959463e-06,
+    1.5252733489960805e-05, 0.00015403530462514614, 0.001333355814678995, 0.009618129107588335,
+    0.055504108664819925,   0.24022650695910155,    0.6931471805599453,    1.0};
 
 __device__ __forceinline__ double exp2_frac(double f) {
     double p = EXP2_C[0];
 #pragma unroll
-    for (int i = 1; i < 14; ++i) p = fma(p, f, EXP2_C[i]);
+    for (int i = 1; i < 12; ++i) p = fma(p, f, EXP2_C[i]);
     return p;
 }
 
@@ -133,17 +132,33 @@ __device__ __forceinline__ int *zslot_e(double *sm) { return (int *)(sm + 4 * CH
 // Extended-exponent accumulate: (A, e) += tm * 2^te, rescaling the running
 // sum to the larger exponent; W (term-weighted displacements) shares the
 // scale of A.
+// w = w * f + d, written in place.  Plain C++ lets the compiler pick the
+// two-address v_fmac form with d as the accumulator, which costs a register
+// copy per update for the loop-carried w; the explicit three-address form
+// avoids it.  Pure arithmetic, no memory access.
+__device__ __forceinline__ void fma_inplace(double &w, double f, double d) {
+    asm("v_fma_f64 %0, %0, %1, %2" : "+v"(w) : "v"(f), "v"(d));
+}
+
+// Opaque copy: keeps the compiler from merging the owner's displacement with
+// the identical expression in the per-row update, which it would otherwise
+// hoist above both branches and evaluate for finished rows too.
+__device__ __forceinline__ double opaque(double x) {
+    asm("" : "+v"(x));
+    return x;
+}
+
 template <bool WSUM>
 __device__ __forceinline__ void xacc(double &A, int &e, double &Wx, double &Wy, double &Wz, double tm, int te,
                                      double dx, double dy, double dz) {
     const int en = max(e, te);
     const double fo = ldexp(1.0, e - en);
     const double tn = ldexp(tm, te - en);
-    A = fma(A, fo, tn);
+    fma_inplace(A, fo, tn);
     if (WSUM) {
-        Wx = fma(Wx, fo, tn * dx);
-        Wy = fma(Wy, fo, tn * dy);
-        Wz = fma(Wz, fo, tn * dz);
+        fma_inplace(Wx, fo, tn * dx);
+        fma_inplace(Wy, fo, tn * dy);
+        fma_inplace(Wz, fo, tn * dz);
     }
     e = en;
 }
@@ -239,9 +254,9 @@ __device__ void forward_role(const LaunchArgs &a, const SysDesc sd, double *sm) 
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             if (j == jo && own) {
-                const double dx = mimg<BOX>(px[j] - ux, box, ib);
-                const double dy = mimg<BOX>(py[j] - uy, box, ib);
-                const double dz = mimg<BOX>(pz[j] - uz, box, ib);
+                const double dx = mimg<BOX>(px[j] - opaque(ux), box, ib);
+                const double dy = mimg<BOX>(py[j] - opaque(uy), box, ib);
+                const double dz = mimg<BOX>(pz[j] - opaque(uz), box, ib);
                 xacc<WSUM>(A[j], e[j], Wx[j], Wy[j], Wz[j], zm * pd[j], ze + kd[j], dx, dy, dz);
                 const double zz = DEFER ? A[j] * iv[DEFER ? j : 0] : A[j] / (double)(s + 1);
                 const double mz = __builtin_amdgcn_frexp_mant(zz);
@@ -387,9 +402,9 @@ __device__ void backward_role(const LaunchArgs &a, const SysDesc sd, double *sm)
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             if (j == jo && own) {
-                const double dx = mimg<BOX>(ux - px[j], box, ib);
-                const double dy = mimg<BOX>(uy - py[j], box, ib);
-                const double dz = mimg<BOX>(uz - pz[j], box, ib);
+                const double dx = mimg<BOX>(opaque(ux) - px[j], box, ib);
+                const double dy = mimg<BOX>(opaque(uy) - py[j], box, ib);
+                const double dz = mimg<BOX>(opaque(uz) - pz[j], box, ib);
                 xacc<true>(A[j], e[j], Wx[j], Wy[j], Wz[j], zm * pd[j], ze + kd[j], dx, dy, dz);
                 const double zz = DEFER ? A[j] * iv[DEFER ? j : 0] : (s > 0 ? A[j] / (double)s : 0.0);
                 zsm[slot ^ 1] = __builtin_amdgcn_frexp_mant(zz);

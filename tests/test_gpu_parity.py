@@ -213,3 +213,22 @@ def test_distinguishable_forces():
     Ed = k * (d * d).sum()
     assert np.abs(eng.unpack(F, 0) - Fd).max() <= 1e-13 * np.abs(Fd).max()
     assert abs(float(E[0]) - Ed) <= 1e-12 * Ed
+
+
+@pytest.mark.parametrize("scale", [0.6, 1.2, 3.0])
+def test_chain_configuration_renormalisation(scale):
+    """Particles laid end to end: bead P of l sits next to bead 1 of l+1 while
+    each ring's own closing spring is long, so the forward potentials change
+    by hundreds of binary orders of magnitude per step (exercises the
+    accumulator renormalisation)."""
+    N, P = 300, 8
+    rng = np.random.default_rng(11)
+    R = np.zeros((N, P, 3))
+    for l in range(N):
+        R[l, :, 0] = (l + 0.9 * np.arange(P) / (P - 1)) * scale
+    R += rng.normal(0, 0.02, R.shape)
+    s = System(R, beta=1.0)
+    eng, pos = _engine([s])
+    F, E = eng.forces(pos)
+    assert eng.status() == 0
+    _assert_parity(eng, F, E, [s], TOL64)
