@@ -1,0 +1,294 @@
+#!/usr/bin/env python3
+"""Benchmark: bosonic exchange energy + force evaluations per second at
+N = 1024 particles, P = 32 beads on one MI355X.
+
+A step is one evaluation of the whole exchange path (interior springs,
+forward and backward recursions, connection-probability forces, energies)
+for a batch of B independent N=1024, P=32 systems, replayed from a HIP graph
+with positions already resident in HBM.  `value` is B * steps / seconds.
+
+Also reported (same JSON line): the plain one-system-per-call path without a
+graph, a batch-size sweep, the mixed-precision variant, accuracy against the
+CPU oracle, the roofline of the fused kernel measured with HIP events, and
+the CPU oracle's own throughput on the host cores (a bounded sample).
+
+    python bench.py [--steps K] [--warmup W] [--batch B]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "exchange E+F evals/sec at N=1024,P=32 (batched vs plain, 1 GPU)"
+N_HEAD, P_HEAD, BETA = 1024, 32, 1.0
+PEAK_FP64 = 78.6e12  # MI355X FP64 vector peak: 256 CU * 4 SIMD * 16 lanes * 2 flop * 2.4 GHz
+# Algorithmic FP64 flops of one term of one recursion: spring length |d|^2
+# (3 sub + 3 mul + 2 add), exponent (mul + add), the exponential counted as
+# its degree-11 polynomial plus range reduction (11 FMA = 22 flops, + 2),
+# Boltzmann-weight accumulation (mul + add) and the weighted displacement
+# (3 mul + 3 add).  Two recursions of M = N(N+1)/2 terms per evaluation.
+FLOPS_PER_TERM = 8 + 2 + 24 + 2 + 6
+
+
+def flops_per_eval(N: int) -> float:
+    return 2.0 * (N * (N + 1) / 2) * FLOPS_PER_TERM
+
+
+def systems(B, seed0=3, variant="gaussian"):
+    from paper_2305_18025_amd import inputs
+    if variant == "gaussian":
+        return [inputs.gaussian_system(N_HEAD, P_HEAD, seed=seed0 + i) for i in range(B)]
+    return [inputs.cube_system(N_HEAD, P_HEAD, seed=seed0 + i) for i in range(B)]
+
+
+def make_engine(B, precision="fp64", tuning=None):
+    from paper_2305_18025_amd import BosonicExchange
+    kw = {}
+    if tuning:
+        kw = dict(threads=tuning[0], per_thread=tuning[1])
+    return BosonicExchange([N_HEAD] * B, [P_HEAD] * B, [BETA] * B, 1.0, precision=precision, **kw)
+
+
+def time_graph(eng, pos, steps, warmup):
+    """Capture one exchange_forces call in a graph; replay warmup + steps.
+    Returns (wall seconds for `steps`, event-timed ms per launch)."""
+    import torch
+    F = eng.empty()
+    E = torch.empty(eng.S, dtype=torch.float64, device=eng.device)
+    eng.forces(pos, out=F, energy=E)  # eager warm-up before capture
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            eng.forces(pos, out=F, energy=E)
+    torch.cuda.current_stream().wait_stream(side)
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(steps):
+        g.replay()
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, e0.elapsed_time(e1) / steps, (F, E)
+
+
+def time_plain(eng, pos, calls):
+    import torch
+    F = eng.empty()
+    E = torch.empty(eng.S, dtype=torch.float64, device=eng.device)
+    for _ in range(3):
+        eng.forces(pos, out=F, energy=E)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        eng.forces(pos, out=F, energy=E)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / calls
+
+
+def accuracy(eng, F, E, R_list, precision="f80", which=(0,)):
+    import numpy as np
+    import oracle
+    from paper_2305_18025_amd.inputs import omega_p
+    ee = fe = 0.0
+    for s in which:
+        o = oracle.alg1(R_list[s], BETA, 1.0, omega_p(P_HEAD, BETA), precision=precision, extras=False)
+        Fg = eng.unpack(F, s)
+        ee = max(ee, abs(float(E[s]) - o["V"]) / abs(o["V"]))
+        fe = max(fe, float(np.abs(Fg - o["F"]).max() / np.abs(o["F"]).max()))
+    return ee, fe
+
+
+def cpu_baseline(seconds, max_threads=16):
+    """The FP64 C oracle (as it stands) on the host cores: independent
+    N=1024, P=32 evaluations (energy + forces) in a thread pool for about
+    `seconds` of wall time."""
+    import concurrent.futures as cf
+    import oracle
+    from paper_2305_18025_amd.inputs import gaussian_system, omega_p
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    cores = max(1, min(max_threads, avail))
+    oracle.build(force=False)
+    Rs = [gaussian_system(N_HEAD, P_HEAD, seed=1000 + i) for i in range(cores)]
+    w = omega_p(P_HEAD, BETA)
+    deadline = time.perf_counter() + seconds
+
+    def worker(i):
+        n = 0
+        while time.perf_counter() < deadline:
+            oracle.alg1(Rs[i], BETA, 1.0, w, precision="f64", extras=False)
+            n += 1
+        return n
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(cores) as ex:
+        counts = list(ex.map(worker, range(cores)))
+    dt = time.perf_counter() - t0
+    total = sum(counts)
+    return {"value": total / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "sample": "%d evaluations (energy+forces, FP64 Fast PIMD-B in C, N=1024 P=32 Gaussian) "
+                      "on %d host threads in %.1f s" % (total, cores, dt)}
+
+
+def traffic_record(batch):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source and batch size."""
+    path = os.path.join(ROOT, "profiles", "exchange_traffic.json")
+    src = os.path.join(ROOT, "paper_2305_18025_amd", "csrc", "kernels.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernels_hip_sha1") != sha or rec.get("batch") != batch:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--sweep", default="1,8,64,256,512")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="headline and plain only")
+    ap.add_argument("--autotune", action="store_true", help="time candidate launch shapes first")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="only replay the headline launch (for rocprofv3 counter runs), then copy a "
+                         "256 MiB buffer once as the traffic calibration kernel")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this implementation runs on one GPU (one MI355X per box); "
+              "--gpus %d is not supported" % max(args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2305_18025_amd.tune import autotune
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    B = args.batch
+    Rb = systems(B)
+
+    # headline: batched, graph-captured, library launch shape (or autotuned)
+    eng = make_engine(B)
+    pos = eng.pack(Rb)
+    if args.autotune:
+        tuned = autotune(eng, pos, reps=2, use_cache=False)
+    else:
+        tuned = eng.tuning
+    wall, ms_launch, (F, E) = time_graph(eng, pos, args.steps, args.warmup)
+    if args.profile_run:
+        src = torch.empty(256 << 20, dtype=torch.uint8, device=eng.device)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": True, "batch": B, "steps": args.steps, "warmup": args.warmup,
+                          "launch_shape": list(tuned[:2]), "calibration_copy_bytes": 256 << 20}))
+        return
+    value = B * args.steps / wall
+    torch.cuda.synchronize()
+    status = eng.status()
+
+    # plain: one system per call, no graph, default (latency) launch shape
+    eng1 = make_engine(1)
+    pos1 = eng1.pack(Rb[0])
+    sec_plain = time_plain(eng1, pos1, max(100, args.steps))
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "bosonic exchange energy+forces, batch of %d systems, N=1024, P=32, beta=1, m=1, "
+                        "omega_P=sqrt(P)/beta; centroids N(0,1), beads centroid+N(0,0.3^2); one HIP-graph "
+                        "replay of the fused launch per step" % B,
+            "N": N_HEAD, "P": P_HEAD, "batch": B, "precision": "fp64", "graph": True,
+            "launch_shape": {"threads": tuned[0], "per_thread": tuned[1]},
+        },
+        "plain": {"value": 1.0 / sec_plain, "unit": "evals/s", "ms_per_eval": sec_plain * 1e3,
+                  "description": "one system per call, no graph"},
+        "batched_over_plain": value * sec_plain,
+        "device_status": status,
+    }
+    flops = B * flops_per_eval(N_HEAD)
+    achieved = flops / (ms_launch * 1e-3)
+    out["roofline"] = {
+        "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+        "frac": achieved / PEAK_FP64, "traffic": traffic_record(B),
+        "kernel": "pimdb::k_exchange%s<%d, false, false> (fused springs + recursions + forces)"
+                  % ("_wide" if tuned[1] >= 4 else "", tuned[1]),
+        "ms_per_launch_hip_events": ms_launch,
+        "flops_per_launch": flops,
+        "flops_per_term": FLOPS_PER_TERM,
+    }
+
+    if not args.quick:
+        ee, fe = accuracy(eng, F, E, Rb, "f80", which=(0, B - 1))
+        out["accuracy_vs_oracle_f80"] = {"energy_rel": ee, "forces_rel_max": fe, "tolerance": 1e-10}
+        sweep = {}
+        for b in [int(x) for x in args.sweep.split(",") if x]:
+            e_b = make_engine(b)
+            p_b = e_b.pack(Rb[:b] if b <= B else systems(b))
+            w_b, ms_b, _ = time_graph(e_b, p_b, max(5, args.steps // 2), 2)
+            sweep[str(b)] = {"evals_per_s": b * max(5, args.steps // 2) / w_b, "ms_per_launch": ms_b,
+                             "launch_shape": list(e_b.tuning)}
+            del e_b, p_b
+        out["batch_sweep"] = sweep
+        em = make_engine(B, precision="mixed", tuning=tuned[:2])
+        pm = em.pack(Rb)
+        w_m, ms_m, (Fm, Em) = time_graph(em, pm, max(5, args.steps // 2), 2)
+        eem, fem = accuracy(em, Fm, Em, Rb, "f80", which=(0,))
+        out["mixed"] = {"evals_per_s": B * max(5, args.steps // 2) / w_m, "energy_rel": eem,
+                        "forces_rel_max": fem, "tolerance": 1e-5,
+                        "description": "FP32 compensated endpoint-spring lengths, FP64 elsewhere"}
+        del em, pm
+        # distinguishable-particle reference cost (same batch, same launch)
+        Fd = eng.empty()
+        Ed = torch.empty(B, dtype=torch.float64, device=eng.device)
+        eng.distinguishable(pos, Fd, Ed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            eng.distinguishable(pos, Fd, Ed)
+        torch.cuda.synchronize()
+        out["distinguishable"] = {"evals_per_s": B * args.steps / (time.perf_counter() - t0),
+                                  "description": "ring-polymer springs without exchange, same batch"}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
