@@ -117,7 +117,8 @@ int pimdb_set_system(pimdb_t h, int64_t N, int32_t P, double beta, double m, dou
 
 /* A batch of S independent systems, host arrays of length S.  Systems may
  * differ in N, P, beta, m and omega_P.  One evaluation call processes the
- * whole batch in a single kernel launch; the launch order puts the largest
+ * whole batch in two kernel launches (springs and recursions of every system,
+ * then exterior forces and energies); the first launch puts the largest
  * systems first.  Unbinds the workspace, as pimdb_set_system.  On error the
  * handle is left with no system set. */
 int pimdb_set_batch(pimdb_t h, int32_t S, const int64_t *N, const int32_t *P, const double *beta,
@@ -159,8 +160,8 @@ int64_t pimdb_total_elements(pimdb_t h);
 size_t pimdb_workspace_bytes(pimdb_t h);
 
 /* Bind caller-owned device memory (at least pimdb_workspace_bytes, 256-byte
- * aligned) as scratch.  The library clears its counters with a kernel on
- * the handle's stream.  The memory must stay allocated while bound. */
+ * aligned) as scratch.  The library clears its status word with a kernel
+ * on the handle's stream.  The memory must stay allocated while bound. */
 int pimdb_bind_workspace(pimdb_t h, void *dev_ptr, size_t bytes);
 
 /* V^[1,N] for every system -> energy[s].  Computes the interior spring
@@ -169,8 +170,8 @@ int pimdb_exchange_energy(pimdb_t h, const double *pos, double *energy);
 
 /* Energies (energy may be NULL) and forces -grad V^[1,N] (+ trap terms if set)
  * on all beads of all systems.  This is the hot path: one kernel launch runs
- * the interior springs, the forward and backward recursions of every system
- * concurrently, and then the exterior-bead forces. */
+ * the interior springs and the forward and backward recursions of every
+ * system concurrently, a second one the exterior-bead forces and energies. */
 int pimdb_exchange_forces(pimdb_t h, const double *pos, double *forces, double *energy);
 
 /* Bytes of the adjoint state written by pimdb_exchange_energy_save. */

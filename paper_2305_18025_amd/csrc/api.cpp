@@ -31,7 +31,7 @@ struct pimdb_ctx {
     // derived tables (host copies and device copies)
     std::vector<SysDesc> desc;
     int64_t total_elems = 0;
-    int64_t ws_doubles = 0; // after header and counters
+    int64_t ws_doubles = 0; // after the header
     int64_t st_doubles = 0;
     SysDesc *d_desc = nullptr;
     Item *d_items = nullptr; // [fb | f | b | s] item lists back to back
@@ -79,8 +79,6 @@ bool pow2_threads(int t) { return t == 64 || t == 128 || t == 256 || t == 512 ||
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
-int64_t counters_bytes(int S) { return round_up((int64_t)S * 4, 256); }
-
 // Automatic launch shape.  One system: latency first -- the widest
 // workgroup (most waves to hide FP64 latency) holding the system with 1 or 2
 // particles per thread.  Several systems: throughput first -- 4 particles per
@@ -112,7 +110,7 @@ void free_tables(pimdb_t h) {
 // Build descriptors, the launch schedule (largest systems first) and the MD
 // element chunks for the current batch and launch shape; upload them.
 int build_tables(pimdb_t h) {
-    // the workspace layout (counters, per-system regions) depends on the
+    // the workspace layout (per-system regions) depends on the
     // batch and the launch shape: the caller binds a workspace again
     h->ws = nullptr;
     h->ws_bytes = 0;
@@ -204,7 +202,7 @@ int build_tables(pimdb_t h) {
 }
 
 size_t ws_bytes_needed(pimdb_t h) {
-    return (size_t)(WS_HEADER_BYTES + counters_bytes(h->S) + h->ws_doubles * 8);
+    return (size_t)(WS_HEADER_BYTES + h->ws_doubles * 8);
 }
 
 int check_ready(pimdb_t h) {
@@ -219,8 +217,7 @@ LaunchArgs base_args(pimdb_t h) {
     LaunchArgs a{};
     a.sys = h->d_desc;
     a.flags = (int32_t *)h->ws;
-    a.counters = (int32_t *)(h->ws + WS_HEADER_BYTES);
-    a.ws = (double *)(h->ws + WS_HEADER_BYTES + counters_bytes(h->S));
+    a.ws = (double *)(h->ws + WS_HEADER_BYTES);
     a.box = h->box;
     a.inv_box = h->box > 0 ? 1.0 / h->box : 0.0;
     a.trap_w2 = h->trap_w * h->trap_w;
@@ -240,6 +237,8 @@ int run(pimdb_t h, LaunchArgs &a, const Item *items, int n) {
     a.items = items;
     hipError_t e = launch_exchange(a, n, h->threads, h->per_thread, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "exchange launch");
+    e = launch_finalize(a, h->S, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "finalize launch");
     return PIMDB_OK;
 }
 
@@ -393,7 +392,7 @@ int pimdb_bind_workspace(pimdb_t h, void *dev_ptr, size_t bytes) {
     h->ws_bytes = bytes;
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, PIMDB_EDEVICE, "cannot select device");
-    const int64_t nints = (WS_HEADER_BYTES + counters_bytes(h->S > 0 ? h->S : 1)) / 4;
+    const int64_t nints = WS_HEADER_BYTES / 4;
     const int64_t lim = (int64_t)bytes / 4;
     hipError_t e = launch_clear((int32_t *)dev_ptr, std::min(nints, lim), h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "clear workspace");

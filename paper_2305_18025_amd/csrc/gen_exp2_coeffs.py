@@ -1,18 +1,19 @@
-"""Coefficients of the degree-11 polynomial used for 2^f, |f| <= 1/2.
+"""Coefficients of the degree-10 polynomial used for 2^f, |f| <= 1/2.
 
 Minimax fit of the relative error of 2^f on [-1/2, 1/2] by the Remez exchange
 algorithm, in 40-digit arithmetic (mpmath).  The approximation error is about
-3e-18, far below the ~2 ulp of evaluating the polynomial in double by Horner's
-rule, so the result is as accurate as the Taylor series of e^(f ln 2) carried
-to degree 13.  Coefficients are printed lowest degree first, rounded to the
-nearest double; the output is pasted into kernels.hip.
+2.1e-16 (2.8e-16 with the coefficients rounded to double), the size of one
+rounding of the result, so degree 10 is the lowest degree that adds no error
+beyond the ~2 ulp of evaluating the polynomial in double by Horner's rule.
+Coefficients are printed lowest degree first, rounded to the nearest double;
+the output is pasted into kernels.hip (highest degree first).
 
     python gen_exp2_coeffs.py
 """
 import mpmath as mp
 
 mp.mp.dps = 40
-DEG = 11
+DEG = 10
 
 
 def rel_err(c, x):

@@ -76,7 +76,7 @@ struct StLayout {
     static __host__ __device__ inline int64_t total(int N) { return 2 * ((int64_t)N + 1) + 3 * (int64_t)N; }
 };
 
-// Workspace header (bytes): status word, then one arrival counter per system.
+// Workspace header (bytes): the status word.
 constexpr int64_t WS_HEADER_BYTES = 256;
 
 struct LaunchArgs {
@@ -85,8 +85,7 @@ struct LaunchArgs {
     const double *pos;
     double *out;           // forces / gradient (may be null: no force writes)
     double *energy;        // per-system energies (may be null)
-    double *ws;            // workspace doubles (after the header and counters)
-    int32_t *counters;     // per-system arrival counters
+    double *ws;            // workspace doubles (after the header)
     int32_t *flags;        // status word
     double *state;         // adjoint state (M_SAVE writes it, M_ADJOINT reads it)
     const double *gscale;  // adjoint: grad of energy per system
@@ -98,6 +97,7 @@ struct LaunchArgs {
 
 // Kernel launch entry points (kernels.hip).
 hipError_t launch_exchange(const LaunchArgs &a, int nitems, int threads, int per_thread, hipStream_t st);
+hipError_t launch_finalize(const LaunchArgs &a, int S, hipStream_t st);
 hipError_t launch_clear(int32_t *p, int64_t n, hipStream_t st);
 // Element range of one system handled by one workgroup of the MD kernels.
 struct EChunk {

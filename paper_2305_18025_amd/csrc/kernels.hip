@@ -28,12 +28,15 @@
 //    is ever needed and no magnitude is lost to the size of V.  Each term
 //    K(u,v) = exp(-b Etilde[u,v]) = 2^x is formed as mantissa 2^frac(x)
 //    (own polynomial) times 2^round(x).
-// 3. Right-looking recursions.  Thread-owned accumulators: when Z_f[u-1] is
-//    known, every accumulator v >= u adds Z_f[u-1] K(u,v) at once, and the
-//    owner of v = u then holds Z_f[u] = acc/u.  One workgroup barrier per
-//    step; the only serial chain is the owner's multiply-add and rescale.
-//    The backward recursion is the same with rows and columns exchanged.
-//    Forward and backward run concurrently in separate workgroups.
+// 3. Right-looking recursions, blocked.  Thread-owned accumulators: when
+//    Z_f[u-1] is known, every accumulator v >= u adds Z_f[u-1] K(u,v), and
+//    the owner of v = u then holds Z_f[u] = acc/u.  Steps go in blocks of 64:
+//    the wave owning a block's 64 accumulators runs its 64 steps serially
+//    with lane broadcasts, then all waves add the block's 64 terms to every
+//    later accumulator without synchronisation; one workgroup barrier per
+//    block.  The backward recursion is the same with rows and columns
+//    exchanged; forward and backward run concurrently in separate
+//    workgroups.
 // 4. Forces without materialised probabilities.  Pr[v -> u] (u <= v) is the
 //    forward term of accumulator v divided by its sum, times
 //    rho_v = Z_f[v] Z_b[v+1] / Z_f[N] = 1 - Pr[v -> v+1]; likewise the column
@@ -52,28 +55,29 @@
 
 namespace pimdb {
 
-constexpr int CH = 512;                  // particles staged in LDS per chunk
 constexpr double LN2 = 0.6931471805599453;
-constexpr double XLO = -536870912.0;     // -2^29: lower clamp of a term exponent
+constexpr double XLO = -536870912.0;     // -2^29: lower clamp of an exported term exponent
 constexpr double XHI = 268435456.0;      //  2^28: bound on h = -kappa |d_ref|^2
 constexpr int EMIN = -(1 << 30);         // exponent of an empty accumulator
+constexpr int EMASK = -(3 << 29);        // term exponent that adds nothing (below EMIN)
 
 enum StatusBits { ST_NONFINITE_IN = 1, ST_NONFINITE_OUT = 2, ST_RANGE = 4 };
 
-// 2^f for |f| <= 1/2: degree-11 minimax polynomial (relative approximation
-// error 3e-18, below the rounding of its evaluation; coefficients from
-// gen_exp2_coeffs.py), highest degree first.  Kept in constant memory so the
-// wave-uniform coefficients live in scalar registers and every Horner step
-// is one v_fma_f64.
-__constant__ double EXP2_C[12] = {
-    4.4352809446103363e-10, 7.074105626245659e-09, 1.0178198033328528e-07, 1.321543308959463e-06,
-    1.5252733489960805e-05, 0.00015403530462514614, 0.001333355814678995, 0.009618129107588335,
-    0.055504108664819925,   0.24022650695910155,    0.6931471805599453,    1.0};
+// 2^f for |f| <= 1/2: degree-10 minimax polynomial (relative approximation
+// error 2.1e-16, about one rounding; coefficients from gen_exp2_coeffs.py),
+// highest degree first.  Kept in constant memory so the wave-uniform
+// coefficients live in scalar registers and every Horner step is one
+// v_fma_f64.
+constexpr int EXP2_N = 11;
+__constant__ double EXP2_C[EXP2_N] = {
+    7.037278846726901e-09,  1.0208537929657404e-07, 1.3215662835959238e-06, 1.5252658116409854e-05,
+    0.00015403529961127076, 0.0013333558228561767,  0.009618129108034596,   0.05550410866445883,
+    0.24022650695908768,    0.6931471805599497,     1.0};
 
 __device__ __forceinline__ double exp2_frac(double f) {
     double p = EXP2_C[0];
 #pragma unroll
-    for (int i = 1; i < 12; ++i) p = fma(p, f, EXP2_C[i]);
+    for (int i = 1; i < EXP2_N; ++i) p = fma(p, f, EXP2_C[i]);
     return p;
 }
 
@@ -124,339 +128,618 @@ __device__ __forceinline__ void set_flag(int32_t *flags, int bits) {
     __hip_atomic_fetch_or(flags, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// LDS map (doubles): [0,CH) x | [CH,2CH) y | [2CH,3CH) z | [3CH,4CH) lambda |
-// [4CH, 4CH+T) reduction | then 2 broadcast mantissas, 2 broadcast exponents.
-__device__ __forceinline__ double *zslot_m(double *sm) { return sm + 4 * CH + blockDim.x; }
-__device__ __forceinline__ int *zslot_e(double *sm) { return (int *)(sm + 4 * CH + blockDim.x + 2); }
+// ------------------------------------------------------------- recursions
+// Both recursions are blocked in BK = 64 steps (one wave's width).  Row j of
+// thread t holds accumulator q = j T + t, so block b (accumulators
+// [64 b, 64 b + 64)) is row b / W of wave b % W (W = T / 64 waves).
+// Forward, iteration k (block k = steps and accumulators [64 k, 64 k + 64)):
+//   phase A (all waves): the exponentials of block k's own triangle
+//     K(s+1, q+1), s <= q, go to LDS; block k-1's terms for block k's 64
+//     accumulators are summed in slices by up to 4 waves (partial sums to
+//     LDS);
+//   barrier;
+//   phase B: the wave owning block k merges the partial sums and runs the
+//     block's 64 steps serially: at step s each lane q >= s adds
+//     Z_f[s] K(s+1, q+1) (read from LDS), after which the owner lane q = s
+//     holds its final sum and Z_f[s+1] = sum / (s+1) reaches the other lanes
+//     by readlane.  Meanwhile every other accumulator beyond block k adds the
+//     64 terms of block k-1 (the panel), with no synchronisation;
+//   barrier.
+// The backward recursion is the mirror image (blocks descending, rows
+// q <= s, terms (Z_b[l+1]/l) K(q+1, l)).
+//
+// Exponent bookkeeping: an accumulator (A, e) stands for A 2^e; a term
+// t 2^te is added as A += t 2^(te - e) while te - e <= RENORM, so A stays
+// below 2^(RENORM + 13) and terms more than 2^1074 below A underflow
+// harmlessly.  A larger term (rare: a much closer pair than any before)
+// first moves the reference: A, W scaled by 2^(e - te), e = te.
+constexpr int BK = 64;
+constexpr int RENORM = 960;
+constexpr int KSPLIT = 4;   // waves that share the previous block's terms for the diagonal rows
+constexpr int KTRI = BK * (BK + 1) / 2;
 
-// Extended-exponent accumulate: (A, e) += tm * 2^te, rescaling the running
-// sum to the larger exponent; W (term-weighted displacements) shares the
-// scale of A.
-// w = w * f + d, written in place.  Plain C++ lets the compiler pick the
-// two-address v_fmac form with d as the accumulator, which costs a register
-// copy per update for the loop-carried w; the explicit three-address form
-// avoids it.  Pure arithmetic, no memory access.
-__device__ __forceinline__ void fma_inplace(double &w, double f, double d) {
-    asm("v_fma_f64 %0, %0, %1, %2" : "+v"(w) : "v"(f), "v"(d));
+// LDS map (doubles):
+//   [L_STG, +3*8*BK)   ring of 3 staged blocks, per particle
+//                      {x1, y1, z1, xP, yP, zP, h, -}: bead-1 and bead-P
+//                      points and h = -kappa |r^P - r_ref^1|^2
+//   [L_ZM, +3*BK)      ring of 3 blocks of broadcast mantissas, per step
+//   [L_ZE, +3*BK/2)    matching exponents (ints)
+//   [L_KP, +KTRI)      the diagonal block's exponentials: mantissas
+//   [L_KN, +KTRI/2)    and exponents (ints), packed triangle
+//   [L_PA, +KSPLIT*4*BK)  partial sums {A, Wx, Wy, Wz} per wave and lane
+//   [L_PE, +KSPLIT*BK/2)  their exponents (ints)
+//   [LDS_RED, +T)      block reduction scratch
+constexpr int L_STG = 0;
+constexpr int L_ZM = 3 * 8 * BK;
+constexpr int L_ZE = L_ZM + 3 * BK;
+constexpr int L_KP = L_ZE + 3 * BK / 2;
+constexpr int L_KN = L_KP + KTRI;
+constexpr int L_PA = L_KN + KTRI / 2 + 1;
+constexpr int L_PE = L_PA + KSPLIT * 4 * BK;
+constexpr int LDS_RED = L_PE + KSPLIT * BK / 2;
+
+__device__ __forceinline__ double *stg_block(double *sm, int b) { return sm + L_STG + (b % 3) * 8 * BK; }
+__device__ __forceinline__ double *zm_block(double *sm, int b) { return sm + L_ZM + (b % 3) * BK; }
+__device__ __forceinline__ int *ze_block(double *sm, int b) { return (int *)(sm + L_ZE) + (b % 3) * BK; }
+__device__ __forceinline__ int *kn_base(double *sm) { return (int *)(sm + L_KN); }
+__device__ __forceinline__ int *pe_base(double *sm) { return (int *)(sm + L_PE); }
+
+// Packed triangle of the diagonal block: forward row i_s holds lanes
+// [i_s, 64), backward row i_s holds lanes [0, i_s].
+template <bool FWD>
+__device__ __forceinline__ int tri_index(int is, int lane) {
+    return FWD ? is * BK - (is * (is - 1)) / 2 + (lane - is) : (is * (is + 1)) / 2 + lane;
 }
 
-// Opaque copy: keeps the compiler from merging the owner's displacement with
-// the identical expression in the per-row update, which it would otherwise
-// hoist above both branches and evaluate for finished rows too.
-__device__ __forceinline__ double opaque(double x) {
-    asm("" : "+v"(x));
-    return x;
+__device__ __forceinline__ int add_sat(int a, int b) { return __builtin_elementwise_add_sat(a, b); }
+__device__ __forceinline__ int sub_sat(int a, int b) { return __builtin_elementwise_sub_sat(a, b); }
+
+// Accumulator of one row: A 2^e and the term-weighted displacements W 2^e.
+struct Acc {
+    double A, Wx, Wy, Wz;
+    int e;
+};
+
+// Move the reference of (A, W) to te if the term t 2^te is more than
+// 2^RENORM above it; returns te - e for the (possibly new) reference.
+template <bool WSUM>
+__device__ __forceinline__ int acc_shift(Acc &r, int te) {
+    int k = sub_sat(te, r.e);
+    if (k > RENORM) {
+        r.A = ldexp(r.A, -k);
+        if (WSUM) {
+            r.Wx = ldexp(r.Wx, -k);
+            r.Wy = ldexp(r.Wy, -k);
+            r.Wz = ldexp(r.Wz, -k);
+        }
+        r.e = te;
+        k = 0;
+    }
+    return k;
 }
 
 template <bool WSUM>
-__device__ __forceinline__ void xacc(double &A, int &e, double &Wx, double &Wy, double &Wz, double tm, int te,
-                                     double dx, double dy, double dz) {
-    const int en = max(e, te);
-    const double fo = ldexp(1.0, e - en);
-    const double tn = ldexp(tm, te - en);
-    fma_inplace(A, fo, tn);
+__device__ __forceinline__ void acc_add(Acc &r, double t, int k, double dx, double dy, double dz) {
+    const double tn = ldexp(t, k);
+    r.A += tn;
     if (WSUM) {
-        fma_inplace(Wx, fo, tn * dx);
-        fma_inplace(Wy, fo, tn * dy);
-        fma_inplace(Wz, fo, tn * dz);
+        r.Wx = fma(tn, dx, r.Wx);
+        r.Wy = fma(tn, dy, r.Wy);
+        r.Wz = fma(tn, dz, r.Wz);
     }
-    e = en;
 }
 
-// 2^x as mantissa p in [0.7, 1.42] and integer exponent n, x >= XLO.
+// Merge another accumulator into r.
+template <bool WSUM>
+__device__ __forceinline__ void acc_merge(Acc &r, const Acc &o) {
+    const int en = max(r.e, o.e);
+    const int a = sub_sat(r.e, en), b = sub_sat(o.e, en);
+    r.A = ldexp(r.A, a) + ldexp(o.A, b);
+    if (WSUM) {
+        r.Wx = ldexp(r.Wx, a) + ldexp(o.Wx, b);
+        r.Wy = ldexp(r.Wy, a) + ldexp(o.Wy, b);
+        r.Wz = ldexp(r.Wz, a) + ldexp(o.Wz, b);
+    }
+    r.e = en;
+}
+
+// 2^x as mantissa p in [0.7, 1.42] and integer exponent n; n saturates for
+// |x| >= 2^31 (such terms then add nothing).
 __device__ __forceinline__ void exp2x(double x, double &p, int &n) {
-    x = fmax(x, XLO);
     const double r = rint(x);
     p = exp2_frac(x - r);
     n = (int)r;
 }
 
-// --------------------------------------------------------------- forward
-// Accumulator v (0-based q) sums Z_f[u-1] K(u, v) over u <= v, u = s + 1 at
-// step s, with K(u,v) = 2^(kappa |r_v^P - r_u^1|^2 + h_v) and
-// h_v = -kappa |r_v^P - r_ref^1|^2, ref = v+1 (v < N) or v (v = N).
-// The diagonal K(v,v) does not depend on the recursion and is precomputed,
-// so the owner of step s only multiplies, adds, rescales and broadcasts
-// before the other terms of the step are formed.  Owners keep their results
-// in registers; nothing is written to global memory inside the step loop.
-template <int J, bool BOX, bool MIXED, bool WSUM>
-__device__ void forward_role(const LaunchArgs &a, const SysDesc sd, double *sm) {
-    // J <= 4: owners keep results in registers until the loop ends; J = 8
-    // has no registers to spare and stores them as they are produced.
-    constexpr bool DEFER = J <= 4;
-    const int t = threadIdx.x, T = blockDim.x, N = sd.N;
-    const size_t NN = (size_t)N;
-    const double *__restrict__ b1 = a.pos + sd.off;                        // bead 1 plane
-    const double *__restrict__ bP = a.pos + sd.off + (size_t)(sd.P - 1) * 3 * NN; // bead P plane
-    double *sx = sm, *sy = sm + CH, *sz = sm + 2 * CH;
-    double *zsm = zslot_m(sm);
-    int *zse = zslot_e(sm);
-    const double kap = sd.kappa, box = a.box, ib = a.inv_box;
+// K = 2^(kappa |a - b|^2 + h) and the displacement d = a - b (minimum
+// image when periodic).
+template <bool BOX, bool MIXED>
+__device__ __forceinline__ void kterm(double ax, double ay, double az, double bx, double by, double bz, double h,
+                                      double kap, double box, double ib, double &p, int &n, double &dx, double &dy,
+                                      double &dz) {
+    dx = mimg<BOX>(ax - bx, box, ib);
+    dy = mimg<BOX>(ay - by, box, ib);
+    dz = mimg<BOX>(az - bz, box, ib);
+    exp2x(fma(kap, sqlen<MIXED>(dx, dy, dz), h), p, n);
+}
 
-    double *base = (a.mode & M_SAVE) ? a.state + sd.st : a.ws + sd.ws;
-    double *__restrict__ zm_out = base + ((a.mode & M_SAVE) ? StLayout::zf_m(N) : WsLayout::zf_m(N));
-    double *__restrict__ ze_out = base + ((a.mode & M_SAVE) ? StLayout::zf_e(N) : WsLayout::zf_e(N));
-    double *__restrict__ r_out = base + ((a.mode & M_SAVE) ? StLayout::rf(N) : WsLayout::rf(N));
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
-    double px[J], py[J], pz[J], hl[J], pd[J], iv[DEFER ? J : 1], A[J], Wx[J], Wy[J], Wz[J], om[DEFER ? J : 1];
-    int e[J], kd[J], oe[DEFER ? J : 1];
-    bool range_bad = false;
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const int q = t + j * T;
-        px[j] = py[j] = pz[j] = hl[j] = pd[j] = 0.0;
-        kd[j] = 0;
-        if (DEFER) {
-            om[j] = 0.0;
-            oe[j] = 0;
-            iv[j] = 1.0 / (double)(q + 1);
-        }
-        if (q < N) {
-            px[j] = bP[q];
-            py[j] = bP[NN + q];
-            pz[j] = bP[2 * NN + q];
-            const int r = q < N - 1 ? q + 1 : q;
-            const double ql = sqlen<MIXED>(mimg<BOX>(px[j] - b1[r], box, ib), mimg<BOX>(py[j] - b1[NN + r], box, ib),
-                                           mimg<BOX>(pz[j] - b1[2 * NN + r], box, ib));
-            hl[j] = -kap * ql;
-            range_bad |= !(hl[j] <= XHI);
-            const double qs = sqlen<MIXED>(mimg<BOX>(px[j] - b1[q], box, ib), mimg<BOX>(py[j] - b1[NN + q], box, ib),
-                                           mimg<BOX>(pz[j] - b1[2 * NN + q], box, ib));
-            exp2x(fma(kap, qs, hl[j]), pd[j], kd[j]);
-        }
-        A[j] = 0.0;
-        Wx[j] = Wy[j] = Wz[j] = 0.0;
-        e[j] = EMIN;
+// Accumulator rows of one thread.  Forward: (px, py, pz) = r_q^P and
+// hl = h_q; backward: (px, py, pz) = r_q^1.
+template <int JJ>
+struct Rows {
+    double px[JJ], py[JJ], pz[JJ], hl[JJ];
+    Acc a[JJ];
+};
+
+struct RecCtx {
+    double *sm;
+    const double *b1, *bP; // bead-1 and bead-P planes of the system
+    size_t NN;
+    int N, T, t, W, nblk;
+    double kap, box, ib;
+};
+
+// Staged data of one particle.
+struct Stage {
+    double x1, y1, z1, xP, yP, zP, h;
+};
+
+template <bool BOX, bool MIXED>
+__device__ __forceinline__ Stage stage_load(const RecCtx &c, int b, bool &bad) {
+    Stage g{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int l = b * BK + (c.t & 63);
+    if (l < c.N) {
+        const size_t NN = c.NN;
+        g.x1 = c.b1[l];
+        g.y1 = c.b1[NN + l];
+        g.z1 = c.b1[2 * NN + l];
+        g.xP = c.bP[l];
+        g.yP = c.bP[NN + l];
+        g.zP = c.bP[2 * NN + l];
+        const int r = l < c.N - 1 ? l + 1 : l;
+        g.h = -c.kap * sqlen<MIXED>(mimg<BOX>(g.xP - c.b1[r], c.box, c.ib),
+                                     mimg<BOX>(g.yP - c.b1[NN + r], c.box, c.ib),
+                                     mimg<BOX>(g.zP - c.b1[2 * NN + r], c.box, c.ib));
+        bad |= !(g.h <= XHI);
     }
-    if (range_bad) set_flag(a.flags, ST_RANGE);
-    if (t == 0) {
-        zsm[0] = 1.0; // Z_f[0] = 1  (V^[1,0] = 0)
-        zse[0] = 0;
-    }
-    int jo = 0, to = 0; // owner of step s: row jo, thread to (s = jo*T + to)
-    for (int s = 0; s < N; ++s) {
-        const int li = s % CH;
-        if (li == 0) {
-            const int n = min(CH, N - s);
-            for (int i = t; i < n; i += T) {
-                sx[i] = b1[s + i];
-                sy[i] = b1[NN + s + i];
-                sz[i] = b1[2 * NN + s + i];
-            }
-            __syncthreads();
-        }
-        const int slot = s & 1;
-        const double zm = zsm[slot];
-        const int ze = zse[slot];
-        const double ux = sx[li], uy = sy[li], uz = sz[li];
-        const bool own = t == to;
-        // owner of step s: diagonal term, Z_f[s+1] = A / (s+1), broadcast
+    return g;
+}
+
+__device__ __forceinline__ void stage_store(const RecCtx &c, int b, const Stage &g) {
+    double *S = stg_block(c.sm, b) + 8 * (c.t & 63);
+    S[0] = g.x1;
+    S[1] = g.y1;
+    S[2] = g.z1;
+    S[3] = g.xP;
+    S[4] = g.yP;
+    S[5] = g.zP;
+    S[6] = g.h;
+}
+
+// The coming term's step data: forward the bead-1 point of u, backward the
+// bead-P point of l and h_l.
+template <bool FWD>
+__device__ __forceinline__ void step_point(const double *S, int i, double &x, double &y, double &z, double &h) {
+    const double *u = S + 8 * i + (FWD ? 0 : 3);
+    x = u[0];
+    y = u[1];
+    z = u[2];
+    h = FWD ? 0.0 : u[3];
+}
+
+// Terms of one step for rows [LO, HI), formed in lockstep (each stage of
+// the exponential for every row before the next), so the chains of
+// different rows interleave.  With 3 or more rows per thread they go in
+// groups of 2 (register budget: 3 waves per SIMD).
+template <bool FWD, int LO, int HI, int JJ, bool BOX, bool MIXED, bool WSUM>
+__device__ __forceinline__ void panel_step(Rows<JJ> &R, const RecCtx &c, double zm, int ze, double ux, double uy,
+                                           double uz, double uh) {
+    constexpr int GM = JJ >= 3 ? 2 : 4;
+    if constexpr (HI - LO > GM) {
+        panel_step<FWD, LO, LO + GM, JJ, BOX, MIXED, WSUM>(R, c, zm, ze, ux, uy, uz, uh);
+        __builtin_amdgcn_sched_barrier(0);
+        panel_step<FWD, LO + GM, HI, JJ, BOX, MIXED, WSUM>(R, c, zm, ze, ux, uy, uz, uh);
+    } else if constexpr (HI > LO) {
+        constexpr int G = HI - LO;
+        double x[G], r[G], f[G], p[G], dx[G], dy[G], dz[G];
+        int k[G];
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
-            if (j == jo && own) {
-                const double dx = mimg<BOX>(px[j] - opaque(ux), box, ib);
-                const double dy = mimg<BOX>(py[j] - opaque(uy), box, ib);
-                const double dz = mimg<BOX>(pz[j] - opaque(uz), box, ib);
-                xacc<WSUM>(A[j], e[j], Wx[j], Wy[j], Wz[j], zm * pd[j], ze + kd[j], dx, dy, dz);
-                const double zz = DEFER ? A[j] * iv[DEFER ? j : 0] : A[j] / (double)(s + 1);
-                const double mz = __builtin_amdgcn_frexp_mant(zz);
-                const int zx = e[j] + __builtin_amdgcn_frexp_exp(zz);
-                zsm[slot ^ 1] = mz;
-                zse[slot ^ 1] = zx;
-                if (DEFER) {
-                    om[DEFER ? j : 0] = mz;
-                    oe[DEFER ? j : 0] = zx;
-                } else {
-                    zm_out[s + 1] = mz;
-                    ze_out[s + 1] = (double)zx;
-                    if (WSUM) {
-                        const double ia = 1.0 / A[j];
-                        r_out[s] = Wx[j] * ia;
-                        r_out[NN + s] = Wy[j] * ia;
-                        r_out[2 * NN + s] = Wz[j] * ia;
-                    }
-                }
+        for (int g = 0; g < G; ++g) {
+            const int j = LO + g;
+            if (FWD) {
+                dx[g] = mimg<BOX>(R.px[j] - ux, c.box, c.ib);
+                dy[g] = mimg<BOX>(R.py[j] - uy, c.box, c.ib);
+                dz[g] = mimg<BOX>(R.pz[j] - uz, c.box, c.ib);
+            } else {
+                dx[g] = mimg<BOX>(ux - R.px[j], c.box, c.ib);
+                dy[g] = mimg<BOX>(uy - R.py[j], c.box, c.ib);
+                dz[g] = mimg<BOX>(uz - R.pz[j], c.box, c.ib);
             }
         }
-        // every later accumulator v > s adds Z_f[s] K(s+1, v)
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
-            const int q = t + j * T;
-            if (q > s && q < N) {
-                const double dx = mimg<BOX>(px[j] - ux, box, ib);
-                const double dy = mimg<BOX>(py[j] - uy, box, ib);
-                const double dz = mimg<BOX>(pz[j] - uz, box, ib);
-                double p;
-                int kx;
-                exp2x(fma(kap, sqlen<MIXED>(dx, dy, dz), hl[j]), p, kx);
-                xacc<WSUM>(A[j], e[j], Wx[j], Wy[j], Wz[j], zm * p, ze + kx, dx, dy, dz);
-            }
-        }
-        if (++to == T) {
-            to = 0;
-            ++jo;
-        }
-        __syncthreads();
-    }
-    // results: Z_f[v] (v = 1..N) and the forward-weighted mean displacement
-    if (t == 0) {
-        zm_out[0] = 1.0;
-        ze_out[0] = 0.0;
-    }
+        for (int g = 0; g < G; ++g) x[g] = fma(c.kap, sqlen<MIXED>(dx[g], dy[g], dz[g]), FWD ? R.hl[LO + g] : uh);
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const int q = t + j * T;
-        if (DEFER && q < N) {
-            zm_out[q + 1] = om[DEFER ? j : 0];
-            ze_out[q + 1] = (double)oe[DEFER ? j : 0];
-            if (WSUM) {
-                const double ia = 1.0 / A[j];
-                r_out[q] = Wx[j] * ia;
-                r_out[NN + q] = Wy[j] * ia;
-                r_out[2 * NN + q] = Wz[j] * ia;
-            }
+        for (int g = 0; g < G; ++g) r[g] = rint(x[g]);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            f[g] = x[g] - r[g];
+            p[g] = EXP2_C[0];
+        }
+#pragma unroll
+        for (int i = 1; i < EXP2_N; ++i) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) p[g] = fma(p[g], f[g], EXP2_C[i]);
+        }
+        bool big = false;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            k[g] = sub_sat(add_sat(ze, (int)r[g]), R.a[LO + g].e);
+            big |= k[g] > RENORM;
+        }
+        if (big) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) k[g] = acc_shift<WSUM>(R.a[LO + g], add_sat(ze, (int)r[g]));
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc_add<WSUM>(R.a[LO + g], zm * p[g], k[g], dx[g], dy[g], dz[g]);
+    }
+}
+
+// Panel: rows [LO, HI) add the terms of the steps of block blk.
+template <bool FWD, int LO, int HI, int JJ, bool BOX, bool MIXED, bool WSUM>
+__device__ __forceinline__ void panel(Rows<JJ> &R, const RecCtx &c, int blk) {
+    if constexpr (HI > LO) {
+        const int nst = min(BK, c.N - blk * BK);
+        const double *S = stg_block(c.sm, blk);
+        const double *Z = zm_block(c.sm, blk);
+        const int *E = ze_block(c.sm, blk);
+        int i = FWD ? 0 : nst - 1;
+        double ux, uy, uz, uh;
+        step_point<FWD>(S, i, ux, uy, uz, uh);
+        double zm = Z[i];
+        int ze = E[i];
+        for (int n = 0; n < nst; ++n) {
+            // next step's values are read before this step's arithmetic
+            const int i2 = FWD ? min(i + 1, BK - 1) : max(i - 1, 0);
+            double vx, vy, vz, vh;
+            step_point<FWD>(S, i2, vx, vy, vz, vh);
+            const double zm2 = Z[i2];
+            const int ze2 = E[i2];
+            panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM>(R, c, zm, ze, ux, uy, uz, uh);
+            ux = vx;
+            uy = vy;
+            uz = vz;
+            uh = vh;
+            zm = zm2;
+            ze = ze2;
+            i = i2;
         }
     }
 }
 
-// --------------------------------------------------------------- backward
-// Accumulator u (0-based q) sums (Z_b[l+1]/l) K(u, l) over l >= u, l = s + 1
-// at step s (descending), K(u,l) = 2^(kappa |r_l^P - r_u^1|^2 + h_l); h_l is
-// staged in LDS with the bead-P positions.  Diagonal precomputed as in the
-// forward recursion.
-template <int J, bool BOX, bool MIXED>
-__device__ void backward_role(const LaunchArgs &a, const SysDesc sd, double *sm) {
-    constexpr bool DEFER = J <= 4;
-    const int t = threadIdx.x, T = blockDim.x, N = sd.N;
-    const size_t NN = (size_t)N;
-    const double *__restrict__ b1 = a.pos + sd.off;
-    const double *__restrict__ bP = a.pos + sd.off + (size_t)(sd.P - 1) * 3 * NN;
-    double *sx = sm, *sy = sm + CH, *sz = sm + 2 * CH, *sh = sm + 3 * CH;
-    double *zsm = zslot_m(sm);
-    int *zse = zslot_e(sm);
-    const double kap = sd.kappa, box = a.box, ib = a.inv_box;
-
-    double *base = a.ws + sd.ws;
-    double *__restrict__ zm_out = base + WsLayout::zb_m(N);
-    double *__restrict__ ze_out = base + WsLayout::zb_e(N);
-    double *__restrict__ r_out = base + WsLayout::rb(N);
-
-    double px[J], py[J], pz[J], pd[J], iv[DEFER ? J : 1], A[J], Wx[J], Wy[J], Wz[J];
-    int e[J], kd[J];
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const int q = t + j * T;
-        px[j] = py[j] = pz[j] = pd[j] = 0.0;
-        kd[j] = 0;
-        if (DEFER) iv[j] = q > 0 ? 1.0 / (double)q : 0.0;
-        if (q < N) {
-            px[j] = b1[q];
-            py[j] = b1[NN + q];
-            pz[j] = b1[2 * NN + q];
-            const double vx = bP[q], vy = bP[NN + q], vz = bP[2 * NN + q];
-            const int r = q < N - 1 ? q + 1 : q;
-            const double ql = sqlen<MIXED>(mimg<BOX>(vx - b1[r], box, ib), mimg<BOX>(vy - b1[NN + r], box, ib),
-                                           mimg<BOX>(vz - b1[2 * NN + r], box, ib));
-            const double qs = sqlen<MIXED>(mimg<BOX>(vx - px[j], box, ib), mimg<BOX>(vy - py[j], box, ib),
-                                           mimg<BOX>(vz - pz[j], box, ib));
-            exp2x(fma(kap, qs, -kap * ql), pd[j], kd[j]);
+// Phase A1: exponentials of block k's triangle into LDS.  Wave w takes the
+// steps i_s = w, w + W, ...; lane i the accumulator 64 k + i.
+template <bool FWD, bool BOX, bool MIXED>
+__device__ __forceinline__ void diag_terms(const RecCtx &c, int k) {
+    const int lane = c.t & 63, w = c.t >> 6;
+    const int nst = min(BK, c.N - k * BK);
+    const double *S = stg_block(c.sm, k);
+    const double *me = S + 8 * lane;
+    double *KP = c.sm + L_KP;
+    int *KN = kn_base(c.sm);
+    for (int is = w; is < nst; is += c.W) {
+        const bool valid = FWD ? lane >= is : lane <= is;
+        double ux, uy, uz, uh, p, dx, dy, dz;
+        int n;
+        step_point<FWD>(S, is, ux, uy, uz, uh);
+        if (FWD)
+            kterm<BOX, MIXED>(me[3], me[4], me[5], ux, uy, uz, me[6], c.kap, c.box, c.ib, p, n, dx, dy, dz);
+        else
+            kterm<BOX, MIXED>(ux, uy, uz, me[0], me[1], me[2], uh, c.kap, c.box, c.ib, p, n, dx, dy, dz);
+        if (valid) {
+            const int ix = tri_index<FWD>(is, lane);
+            KP[ix] = p;
+            KN[ix] = n;
         }
-        A[j] = 0.0;
-        Wx[j] = Wy[j] = Wz[j] = 0.0;
-        e[j] = EMIN;
     }
-    if (t == 0) {
-        const double zz = 1.0 / (double)N; // broadcast Z_b[N+1] / N, Z_b[N+1] = 1
-        zsm[(N - 1) & 1] = __builtin_amdgcn_frexp_mant(zz);
-        zse[(N - 1) & 1] = __builtin_amdgcn_frexp_exp(zz);
+}
+
+// Phase A2: wave w < KSPLIT sums the terms of its slice of block prev's
+// steps for block k's accumulators (lane i: 64 k + i) into LDS.
+template <bool FWD, bool BOX, bool MIXED, bool WSUM>
+__device__ __forceinline__ void diag_partial(const RecCtx &c, int k, int prev) {
+    const int lane = c.t & 63, w = c.t >> 6;
+    const int ns = min(KSPLIT, c.W);
+    if (w >= ns) return;
+    const double *me = stg_block(c.sm, k) + 8 * lane;
+    Rows<1> R;
+    if (FWD) {
+        R.px[0] = me[3];
+        R.py[0] = me[4];
+        R.pz[0] = me[5];
+        R.hl[0] = me[6];
+    } else {
+        R.px[0] = me[0];
+        R.py[0] = me[1];
+        R.pz[0] = me[2];
+        R.hl[0] = 0.0;
     }
-    bool range_bad = false;
-    int jo = (N - 1) / T, to = (N - 1) - jo * T; // owner of step s
-    for (int s = N - 1; s >= 0; --s) {
-        const int lo = s - s % CH;
-        if (s == N - 1 || s % CH == CH - 1) {
-            const int n = s - lo + 1;
-            for (int i = t; i < n; i += T) {
-                const int l = lo + i;
-                const double x = bP[l], y = bP[NN + l], z = bP[2 * NN + l];
-                const int r = l < N - 1 ? l + 1 : l;
-                const double dx = mimg<BOX>(x - b1[r], box, ib);
-                const double dy = mimg<BOX>(y - b1[NN + r], box, ib);
-                const double dz = mimg<BOX>(z - b1[2 * NN + r], box, ib);
-                const double h = -kap * sqlen<MIXED>(dx, dy, dz);
-                range_bad |= !(h <= XHI);
-                sx[i] = x;
-                sy[i] = y;
-                sz[i] = z;
-                sh[i] = h;
+    R.a[0] = Acc{0.0, 0.0, 0.0, 0.0, EMIN};
+    const int nst = min(BK, c.N - prev * BK); // previous block: full except the backward top
+    const int i0 = (nst * w) / ns, i1 = (nst * (w + 1)) / ns;
+    const double *S = stg_block(c.sm, prev);
+    const double *Z = zm_block(c.sm, prev);
+    const int *E = ze_block(c.sm, prev);
+    for (int n = i0; n < i1; ++n) {
+        const int i = FWD ? n : nst - 1 - n;
+        double ux, uy, uz, uh;
+        step_point<FWD>(S, i, ux, uy, uz, uh);
+        panel_step<FWD, 0, 1, 1, BOX, MIXED, WSUM>(R, c, Z[i], E[i], ux, uy, uz, uh);
+    }
+    double *PA = c.sm + L_PA + w * 4 * BK + lane;
+    PA[0] = R.a[0].A;
+    PA[BK] = R.a[0].Wx;
+    PA[2 * BK] = R.a[0].Wy;
+    PA[3 * BK] = R.a[0].Wz;
+    pe_base(c.sm)[w * BK + lane] = R.a[0].e;
+}
+
+// Phase B, owner wave: merge the partial sums, then run block k's steps
+// serially on row j (lane i: accumulator 64 k + i).  Afterwards every lane's
+// row is final: its published value goes to the broadcast ring for the
+// panels and its results to global memory.
+template <bool FWD, int j, int JJ, bool BOX, bool MIXED, bool WSUM>
+__device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bool has_prev, double *zm_out,
+                                         double *ze_out, double *r_out) {
+    const int lane = c.t & 63, q = k * BK + lane, N = c.N;
+    const size_t NN = c.NN;
+    const int nst = min(BK, N - k * BK);
+    Acc &r = R.a[j];
+    if (has_prev) {
+        const int ns = min(KSPLIT, c.W);
+        for (int w = 0; w < ns; ++w) {
+            const double *PA = c.sm + L_PA + w * 4 * BK + lane;
+            acc_merge<WSUM>(r, Acc{PA[0], PA[BK], PA[2 * BK], PA[3 * BK], pe_base(c.sm)[w * BK + lane]});
+        }
+    }
+    const double ivd = FWD ? 1.0 / (double)(q + 1) : (q > 0 ? 1.0 / (double)q : 0.0);
+    const double *S = stg_block(c.sm, k);
+    const double *KP = c.sm + L_KP;
+    const int *KN = kn_base(c.sm);
+    const int first = FWD ? 0 : nst - 1;
+    double zm = zm_block(c.sm, k)[first];
+    int ze = ze_block(c.sm, k)[first];
+    for (int i = 0; i < nst; ++i) {
+        const int is = FWD ? i : nst - 1 - i;
+        const bool live = FWD ? lane >= is : lane <= is;
+        const int ix = tri_index<FWD>(is, live ? lane : is);
+        const double p = KP[ix];
+        const int n = KN[ix];
+        double dx = 0.0, dy = 0.0, dz = 0.0;
+        if (WSUM) {
+            double ux, uy, uz, uh;
+            step_point<FWD>(S, is, ux, uy, uz, uh);
+            if (FWD) {
+                dx = mimg<BOX>(R.px[j] - ux, c.box, c.ib);
+                dy = mimg<BOX>(R.py[j] - uy, c.box, c.ib);
+                dz = mimg<BOX>(R.pz[j] - uz, c.box, c.ib);
+            } else {
+                dx = mimg<BOX>(ux - R.px[j], c.box, c.ib);
+                dy = mimg<BOX>(uy - R.py[j], c.box, c.ib);
+                dz = mimg<BOX>(uz - R.pz[j], c.box, c.ib);
             }
-            __syncthreads();
         }
-        const bool own = t == to;
-        const int li = s - lo;
-        const int slot = s & 1;
-        const double zm = zsm[slot];
-        const int ze = zse[slot];
-        const double ux = sx[li], uy = sy[li], uz = sz[li], h = sh[li];
-        // owner of step s: Z_b[s+1] = A; broadcast Z_b[s+1] / s
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-            if (j == jo && own) {
-                const double dx = mimg<BOX>(opaque(ux) - px[j], box, ib);
-                const double dy = mimg<BOX>(opaque(uy) - py[j], box, ib);
-                const double dz = mimg<BOX>(opaque(uz) - pz[j], box, ib);
-                xacc<true>(A[j], e[j], Wx[j], Wy[j], Wz[j], zm * pd[j], ze + kd[j], dx, dy, dz);
-                const double zz = DEFER ? A[j] * iv[DEFER ? j : 0] : (s > 0 ? A[j] / (double)s : 0.0);
-                zsm[slot ^ 1] = __builtin_amdgcn_frexp_mant(zz);
-                zse[slot ^ 1] = e[j] + __builtin_amdgcn_frexp_exp(zz);
-                if (!DEFER) {
-                    zm_out[s + 1] = __builtin_amdgcn_frexp_mant(A[j]);
-                    ze_out[s + 1] = (double)(e[j] + __builtin_amdgcn_frexp_exp(A[j]));
-                    const double ia = 1.0 / A[j];
-                    r_out[s] = Wx[j] * ia;
-                    r_out[NN + s] = Wy[j] * ia;
-                    r_out[2 * NN + s] = Wz[j] * ia;
+        const int te = live ? add_sat(ze, n) : EMASK;
+        int kk = sub_sat(te, r.e);
+        if (kk > RENORM) kk = acc_shift<WSUM>(r, te);
+        acc_add<WSUM>(r, zm * p, kk, dx, dy, dz);
+        // the owner (lane is) is complete: broadcast its scaled sum
+        const double zz = r.A * ivd;
+        zm = readlane_f64(__builtin_amdgcn_frexp_mant(zz), is);
+        ze = __builtin_amdgcn_readlane(r.e + __builtin_amdgcn_frexp_exp(zz), is);
+    }
+    if (q < N) {
+        const double zz = r.A * ivd;
+        const double mz = __builtin_amdgcn_frexp_mant(zz);
+        const int ez = r.e + __builtin_amdgcn_frexp_exp(zz);
+        const int sp = FWD ? q + 1 : q - 1; // step that reads this value
+        if (sp >= 0 && sp < N) {
+            zm_block(c.sm, sp / BK)[sp % BK] = mz;
+            ze_block(c.sm, sp / BK)[sp % BK] = ez;
+        }
+        if (FWD) { // Z_f[q+1]
+            zm_out[q + 1] = mz;
+            ze_out[q + 1] = (double)ez;
+        } else { // Z_b[q+1]
+            zm_out[q + 1] = __builtin_amdgcn_frexp_mant(r.A);
+            ze_out[q + 1] = (double)(r.e + __builtin_amdgcn_frexp_exp(r.A));
+        }
+        if (WSUM) {
+            const double ia = 1.0 / r.A;
+            r_out[q] = r.Wx * ia;
+            r_out[NN + q] = r.Wy * ia;
+            r_out[2 * NN + q] = r.Wz * ia;
+        }
+    }
+}
+
+// Phase B of one wave.  Forward: live rows [LO, JJ) (blocks >= k);
+// backward: live rows [0, HI) (blocks <= k).  DG: this wave owns block k
+// (row LO forward, row HI-1 backward).
+template <bool FWD, int LO, int HI, bool DG, int JJ, bool BOX, bool MIXED, bool WSUM>
+__device__ __forceinline__ void wave_iter(Rows<JJ> &R, const RecCtx &c, int k, double *zm_out, double *ze_out,
+                                          double *r_out) {
+    const int prev = FWD ? k - 1 : k + 1;
+    const bool has_prev = FWD ? k > 0 : k + 1 < c.nblk;
+    if constexpr (DG) {
+        constexpr int jd = FWD ? LO : HI - 1;
+        diagonal<FWD, jd, JJ, BOX, MIXED, WSUM>(R, c, k, has_prev, zm_out, ze_out, r_out);
+        if (has_prev) {
+            if (FWD)
+                panel<FWD, LO + 1, HI, JJ, BOX, MIXED, WSUM>(R, c, prev);
+            else
+                panel<FWD, LO, HI - 1, JJ, BOX, MIXED, WSUM>(R, c, prev);
+        }
+    } else {
+        if (has_prev) panel<FWD, LO, HI, JJ, BOX, MIXED, WSUM>(R, c, prev);
+    }
+}
+
+// Runtime (first live row / number of live rows, owner?) -> compiled variant.
+template <bool FWD, int X, int JJ, bool BOX, bool MIXED, bool WSUM>
+__device__ __forceinline__ void wave_dispatch(Rows<JJ> &R, const RecCtx &c, int k, int x, bool dg, double *zm_out,
+                                              double *ze_out, double *r_out) {
+    if constexpr (X <= JJ) {
+        if (x == X) {
+            if (FWD) {
+                if constexpr (X < JJ) {
+                    if (dg)
+                        wave_iter<FWD, X, JJ, true, JJ, BOX, MIXED, WSUM>(R, c, k, zm_out, ze_out, r_out);
+                    else
+                        wave_iter<FWD, X, JJ, false, JJ, BOX, MIXED, WSUM>(R, c, k, zm_out, ze_out, r_out);
+                }
+            } else {
+                if constexpr (X > 0) {
+                    if (dg)
+                        wave_iter<FWD, 0, X, true, JJ, BOX, MIXED, WSUM>(R, c, k, zm_out, ze_out, r_out);
+                    else
+                        wave_iter<FWD, 0, X, false, JJ, BOX, MIXED, WSUM>(R, c, k, zm_out, ze_out, r_out);
                 }
             }
+        } else {
+            wave_dispatch<FWD, X + 1, JJ, BOX, MIXED, WSUM>(R, c, k, x, dg, zm_out, ze_out, r_out);
         }
-        // every earlier accumulator u < s adds (Z_b[s+2]/(s+1)) K(u, s+1)
+    }
+}
+
+template <bool FWD, int JJ, bool BOX, bool MIXED, bool WSUM>
+__device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c) {
+    const int t = c.t, T = c.T, N = c.N, W = c.W, w = t >> 6, nblk = c.nblk;
+    const size_t NN = c.NN;
+    double *zm_out, *ze_out, *r_out;
+    if (FWD) {
+        double *base = (a.mode & M_SAVE) ? a.state + sd.st : a.ws + sd.ws;
+        zm_out = base + ((a.mode & M_SAVE) ? StLayout::zf_m(N) : WsLayout::zf_m(N));
+        ze_out = base + ((a.mode & M_SAVE) ? StLayout::zf_e(N) : WsLayout::zf_e(N));
+        r_out = base + ((a.mode & M_SAVE) ? StLayout::rf(N) : WsLayout::rf(N));
+    } else {
+        double *base = a.ws + sd.ws;
+        zm_out = base + WsLayout::zb_m(N);
+        ze_out = base + WsLayout::zb_e(N);
+        r_out = base + WsLayout::rb(N);
+    }
+    Rows<JJ> R;
+    bool range_bad = false;
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
-            const int q = t + j * T;
-            if (q < s) {
-                const double dx = mimg<BOX>(ux - px[j], box, ib);
-                const double dy = mimg<BOX>(uy - py[j], box, ib);
-                const double dz = mimg<BOX>(uz - pz[j], box, ib);
-                double p;
-                int kx;
-                exp2x(fma(kap, sqlen<MIXED>(dx, dy, dz), h), p, kx);
-                xacc<true>(A[j], e[j], Wx[j], Wy[j], Wz[j], zm * p, ze + kx, dx, dy, dz);
+    for (int j = 0; j < JJ; ++j) {
+        const int q = j * T + t;
+        R.px[j] = R.py[j] = R.pz[j] = R.hl[j] = 0.0;
+        if (q < N) {
+            if (FWD) {
+                R.px[j] = c.bP[q];
+                R.py[j] = c.bP[NN + q];
+                R.pz[j] = c.bP[2 * NN + q];
+                const int r = q < N - 1 ? q + 1 : q;
+                R.hl[j] = -c.kap * sqlen<MIXED>(mimg<BOX>(R.px[j] - c.b1[r], c.box, c.ib),
+                                                 mimg<BOX>(R.py[j] - c.b1[NN + r], c.box, c.ib),
+                                                 mimg<BOX>(R.pz[j] - c.b1[2 * NN + r], c.box, c.ib));
+                range_bad |= !(R.hl[j] <= XHI);
+            } else {
+                R.px[j] = c.b1[q];
+                R.py[j] = c.b1[NN + q];
+                R.pz[j] = c.b1[2 * NN + q];
             }
         }
-        if (--to < 0) {
-            to = T - 1;
-            --jo;
+        R.a[j] = Acc{0.0, 0.0, 0.0, 0.0, EMIN};
+    }
+    // first block staged, first broadcast value: Z_f[0] = 1 (V^[1,0] = 0),
+    // or Z_b[N+1] / N = 1 / N
+    const int b0 = FWD ? 0 : nblk - 1;
+    if (w == 0) stage_store(c, b0, stage_load<BOX, MIXED>(c, b0, range_bad));
+    if (t == 0) {
+        const int s0 = FWD ? 0 : N - 1;
+        const double z0 = FWD ? 1.0 : 1.0 / (double)N;
+        zm_block(c.sm, s0 / BK)[s0 % BK] = __builtin_amdgcn_frexp_mant(z0);
+        ze_block(c.sm, s0 / BK)[s0 % BK] = __builtin_amdgcn_frexp_exp(z0);
+        if (FWD) {
+            zm_out[0] = 1.0;
+            ze_out[0] = 0.0;
+        } else {
+            zm_out[N + 1] = 1.0;
+            ze_out[N + 1] = 0.0;
         }
+    }
+    // loads of the rows are complete before the loop (a wait inside it would
+    // also wait for the staging loads issued there)
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int it = 0; it < nblk; ++it) {
+        const int k = FWD ? it : nblk - 1 - it;
+        const int prev = FWD ? k - 1 : k + 1;
+        const bool has_prev = FWD ? k > 0 : k + 1 < nblk;
+        // phase A; the next block is staged by the last wave (its loads are
+        // issued first and land in LDS before the barrier; its ring slot last
+        // held block k-2, which is no longer read)
+        const int nb = FWD ? k + 1 : k - 1;
+        const bool stage = w == W - 1 && nb >= 0 && nb < nblk;
+        Stage g{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (stage) g = stage_load<BOX, MIXED>(c, nb, range_bad);
+        diag_terms<FWD, BOX, MIXED>(c, k);
+        if (has_prev) diag_partial<FWD, BOX, MIXED, WSUM>(c, k, prev);
+        if (stage) stage_store(c, nb, g);
+        __syncthreads();
+        // phase B
+        int x;
+        bool dg;
+        if (FWD) { // first row j with j W + w >= k
+            x = k <= w ? 0 : (k - w + W - 1) / W;
+            dg = x * W + w == k;
+        } else { // number of rows j with j W + w <= k
+            x = k < w ? 0 : min((k - w) / W + 1, JJ);
+            dg = x > 0 && (x - 1) * W + w == k;
+        }
+        wave_dispatch<FWD, 0, JJ, BOX, MIXED, WSUM>(R, c, k, x, dg, zm_out, ze_out, r_out);
         __syncthreads();
     }
     if (range_bad) set_flag(a.flags, ST_RANGE);
-    // results: Z_b[u] (u = 1..N+1) and the backward-weighted mean displacement
-    if (t == 0) {
-        zm_out[N + 1] = 1.0;
-        ze_out[N + 1] = 0.0;
+}
+
+// Dispatch on the number of rows the system needs, JJ = ceil(N / T) <= J,
+// so that no thread carries rows past the end of a smaller system.
+template <int JJ, int J, bool FWD, bool BOX, bool MIXED, bool WSUM>
+__device__ __forceinline__ void rec_dispatch(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c, int jj) {
+    if constexpr (JJ <= J) {
+        if (jj == JJ)
+            recursion_rows<FWD, JJ, BOX, MIXED, WSUM>(a, sd, c);
+        else
+            rec_dispatch<JJ + 1, J, FWD, BOX, MIXED, WSUM>(a, sd, c, jj);
     }
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const int q = t + j * T;
-        if (DEFER && q < N) {
-            zm_out[q + 1] = __builtin_amdgcn_frexp_mant(A[j]);
-            ze_out[q + 1] = (double)(e[j] + __builtin_amdgcn_frexp_exp(A[j]));
-            const double ia = 1.0 / A[j];
-            r_out[q] = Wx[j] * ia;
-            r_out[NN + q] = Wy[j] * ia;
-            r_out[2 * NN + q] = Wz[j] * ia;
-        }
-    }
+}
+
+template <int J, bool FWD, bool BOX, bool MIXED, bool WSUM>
+__device__ __forceinline__ void recursion_role(const LaunchArgs &a, const SysDesc sd, double *sm) {
+    RecCtx c;
+    c.sm = sm;
+    c.NN = (size_t)sd.N;
+    c.b1 = a.pos + sd.off;
+    c.bP = a.pos + sd.off + (size_t)(sd.P - 1) * 3 * c.NN;
+    c.N = sd.N;
+    c.T = blockDim.x;
+    c.t = threadIdx.x;
+    c.W = c.T / 64;
+    c.nblk = (sd.N + BK - 1) / BK;
+    c.kap = sd.kappa;
+    c.box = a.box;
+    c.ib = a.inv_box;
+    const int jj = (sd.N + c.T - 1) / c.T;
+    rec_dispatch<1, J, FWD, BOX, MIXED, WSUM>(a, sd, c, jj);
 }
 
 // ---------------------------------------------------------------- springs
@@ -465,8 +748,8 @@ __device__ void backward_role(const LaunchArgs &a, const SysDesc sd, double *sm)
 // bead forces -m w_P^2 (2 r^j - r^{j+1} - r^{j-1}) for j = 2..P-1 (Theory,
 // "Force on interior beads"), and the optional trap.  In distinguishable mode
 // every ring closes on itself and all beads are written here.
-template <bool BOX>
-__device__ void springs_role(const LaunchArgs &a, const SysDesc sd, int si, int chunk, double *sm) {
+template <bool BOX, int GB>
+__device__ __forceinline__ void springs_role(const LaunchArgs &a, const SysDesc sd, int si, int chunk, double *sm) {
     const int t = threadIdx.x, T = blockDim.x, N = sd.N, P = sd.P;
     const size_t NN = (size_t)N;
     const int q = chunk * T + t;
@@ -479,58 +762,70 @@ __device__ void springs_role(const LaunchArgs &a, const SysDesc sd, int si, int 
     double esum = 0.0;
     bool bad = false;
     if (q < N) {
-        const double *p0 = a.pos + sd.off;
-        double *fo = wf ? a.out + sd.off : nullptr;
-        double cx = p0[q], cy = p0[NN + q], cz = p0[2 * NN + q];
+        // positions and forces never alias (part of the interface), so the
+        // loads of later beads may be issued ahead of this bead's stores
+        const double *__restrict__ p0 = a.pos + sd.off + q;
+        double *__restrict__ fo = wf ? a.out + sd.off + q : nullptr;
+        double cx = p0[0], cy = p0[NN], cz = p0[2 * NN];
         double vx, vy, vz; // previous bead
         if (dist) {
             const size_t o = (size_t)(P - 1) * 3 * NN;
-            vx = p0[o + q];
-            vy = p0[o + NN + q];
-            vz = p0[o + 2 * NN + q];
+            vx = p0[o];
+            vy = p0[o + NN];
+            vz = p0[o + 2 * NN];
         } else {
             vx = cx; vy = cy; vz = cz;
         }
         double ei = 0.0, et = 0.0;
-        for (int j = 0; j < P; ++j) {
-            bad |= !isfinite(cx) || !isfinite(cy) || !isfinite(cz);
-            double nx, ny, nz;
-            if (j + 1 < P) {
-                const size_t o = (size_t)(j + 1) * 3 * NN;
-                nx = p0[o + q];
-                ny = p0[o + NN + q];
-                nz = p0[o + 2 * NN + q];
-            } else {
-                nx = p0[q];
-                ny = p0[NN + q];
-                nz = p0[2 * NN + q];
+        // beads in groups of GB: the group's loads are all issued before any
+        // of its arithmetic, so the memory latency is paid once per group
+        for (int j0 = 0; j0 < P; j0 += GB) {
+            double gx[GB], gy[GB], gz[GB];
+#pragma unroll
+            for (int u = 0; u < GB; ++u) {
+                const int jn = j0 + u + 1;
+                const size_t o = (size_t)(jn < P ? jn : 0) * 3 * NN;
+                gx[u] = gy[u] = gz[u] = 0.0;
+                if (j0 + u < P) {
+                    gx[u] = p0[o];
+                    gy[u] = p0[o + NN];
+                    gz[u] = p0[o + 2 * NN];
+                }
             }
-            const double ax = mimg<BOX>(cx - nx, box, ib);
-            const double ay = mimg<BOX>(cy - ny, box, ib);
-            const double az = mimg<BOX>(cz - nz, box, ib);
-            if (j + 1 < P || dist) ei += ax * ax + ay * ay + az * az;
-            et += cx * cx + cy * cy + cz * cz;
-            if (wf && ((j > 0 && j < P - 1) || dist)) {
-                const double bx = mimg<BOX>(cx - vx, box, ib);
-                const double by = mimg<BOX>(cy - vy, box, ib);
-                const double bz = mimg<BOX>(cz - vz, box, ib);
-                const size_t o = (size_t)j * 3 * NN;
-                fo[o + q] = scale * (-mw2 * (ax + bx) - trapc * cx);
-                fo[o + NN + q] = scale * (-mw2 * (ay + by) - trapc * cy);
-                fo[o + 2 * NN + q] = scale * (-mw2 * (az + bz) - trapc * cz);
+#pragma unroll
+            for (int u = 0; u < GB; ++u) {
+                const int j = j0 + u;
+                if (j < P) {
+                    const double nx = gx[u], ny = gy[u], nz = gz[u];
+                    bad |= !isfinite(cx) || !isfinite(cy) || !isfinite(cz);
+                    const double ax = mimg<BOX>(cx - nx, box, ib);
+                    const double ay = mimg<BOX>(cy - ny, box, ib);
+                    const double az = mimg<BOX>(cz - nz, box, ib);
+                    if (j + 1 < P || dist) ei += ax * ax + ay * ay + az * az;
+                    et += cx * cx + cy * cy + cz * cz;
+                    if (wf && ((j > 0 && j < P - 1) || dist)) {
+                        const double bx = mimg<BOX>(cx - vx, box, ib);
+                        const double by = mimg<BOX>(cy - vy, box, ib);
+                        const double bz = mimg<BOX>(cz - vz, box, ib);
+                        const size_t oj = (size_t)j * 3 * NN;
+                        fo[oj] = scale * (-mw2 * (ax + bx) - trapc * cx);
+                        fo[oj + NN] = scale * (-mw2 * (ay + by) - trapc * cy);
+                        fo[oj + 2 * NN] = scale * (-mw2 * (az + bz) - trapc * cz);
+                    }
+                    vx = cx; vy = cy; vz = cz;
+                    cx = nx; cy = ny; cz = nz;
+                }
             }
-            vx = cx; vy = cy; vz = cz;
-            cx = nx; cy = ny; cz = nz;
         }
         esum = k * ei + 0.5 * trapc * et;
     }
     if (bad) set_flag(a.flags, ST_NONFINITE_IN);
-    const double tot = block_sum(esum, sm + 4 * CH);
+    const double tot = block_sum(esum, sm + LDS_RED);
     if (t == 0) a.ws[sd.ws + WsLayout::epart(N) + chunk] = tot;
 }
 
 // ---------------------------------------------------------------- finalize
-// Run by the last workgroup of a system to arrive.  Exterior-bead forces
+// One workgroup per system, after the recursions.  Exterior-bead forces
 // (Theory, "Force on exterior beads") written in displacement form:
 //   F_l^P = -m w^2 [ (r_l^P - r_l^{P-1}) + sum_{u<=l} Pr[l->u] (r_l^P - r_u^1)
 //                    + Pr[l->l+1] (r_l^P - r_{l+1}^1) ]
@@ -540,7 +835,7 @@ __device__ void springs_role(const LaunchArgs &a, const SysDesc sd, int si, int 
 // are rho * (weighted mean displacement) from the recursions.  Energy:
 //   V^[1,N] = sum_l E_int(l) + sum_{l<N} s(l,l+1) + s(N,N) - ln(Z_f[N]) / beta.
 template <bool BOX>
-__device__ void finalize(const LaunchArgs &a, const SysDesc sd, int si, double *sm) {
+__device__ __forceinline__ void finalize(const LaunchArgs &a, const SysDesc sd, int si, double *red) {
     const int t = threadIdx.x, T = blockDim.x, N = sd.N, P = sd.P;
     const size_t NN = (size_t)N;
     const double *p0 = a.pos + sd.off;
@@ -548,6 +843,7 @@ __device__ void finalize(const LaunchArgs &a, const SysDesc sd, int si, double *
     const bool dist = (a.mode & M_DIST) != 0;
     const bool wf = (a.mode & M_FORCES) && a.out && !dist;
     const bool we = (a.mode & M_ENERGY) && a.energy;
+    if (!wf && !we) return;
     const double *wsb = a.ws + sd.ws;
     const double *fsrc = (a.mode & M_ADJOINT) ? a.state + sd.st : a.ws + sd.ws;
     const double *zfm = fsrc + ((a.mode & M_ADJOINT) ? StLayout::zf_m(N) : WsLayout::zf_m(N));
@@ -624,7 +920,7 @@ __device__ void finalize(const LaunchArgs &a, const SysDesc sd, int si, double *
         }
     }
     if (we) {
-        const double links = block_sum(elink, sm + 4 * CH);
+        const double links = block_sum(elink, red);
         if (t == 0) {
             double E = 0.0;
             for (int c = 0; c < sd.nchunk; ++c) E += wsb[WsLayout::epart(N) + c];
@@ -637,38 +933,26 @@ __device__ void finalize(const LaunchArgs &a, const SysDesc sd, int si, double *
 }
 
 // ------------------------------------------------------------ fused kernel
+// One launch runs every recursion and spring block of the batch; the
+// exterior forces and energies follow in a second launch (k_finalize), so
+// the results of all workgroups are visible to it through the stream order
+// alone: no grid-wide flag, and no device-scope cache maintenance per
+// workgroup.
 template <int J, bool BOX, bool MIXED>
 __device__ __forceinline__ void exchange_body(const LaunchArgs &a) {
     extern __shared__ double sm[];
-    __shared__ int s_last;
     const Item it = a.items[blockIdx.x];
     const SysDesc sd = a.sys[it.sys];
     if (it.role == ROLE_FORWARD) {
         if (a.mode & M_WSUM)
-            forward_role<J, BOX, MIXED, true>(a, sd, sm);
+            recursion_role<J, true, BOX, MIXED, true>(a, sd, sm);
         else
-            forward_role<J, BOX, MIXED, false>(a, sd, sm);
+            recursion_role<J, true, BOX, MIXED, false>(a, sd, sm);
     } else if (it.role == ROLE_BACKWARD) {
-        backward_role<J, BOX, MIXED>(a, sd, sm);
+        recursion_role<J, false, BOX, MIXED, true>(a, sd, sm);
     } else {
-        springs_role<BOX>(a, sd, it.sys, it.idx, sm);
-    }
-    // Arrival: release this workgroup's global writes, count it, and let the
-    // last workgroup of the system (acquire) compute the exterior forces.
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int target = ((a.mode & M_FWD) ? 1 : 0) + ((a.mode & M_BWD) ? 1 : 0) + sd.nchunk;
-        const int old = __hip_atomic_fetch_add(&a.counters[it.sys], 1, __ATOMIC_ACQ_REL,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (old == target - 1);
-    }
-    __syncthreads();
-    if (s_last) {
-        __threadfence();
-        finalize<BOX>(a, sd, it.sys, sm);
-        if (threadIdx.x == 0)
-            __hip_atomic_store(&a.counters[it.sys], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // 1024-thread kernels have 128 registers: smaller bead groups
+        springs_role<BOX, (J >= 4 ? 8 : 4)>(a, sd, it.sys, it.idx, sm);
     }
 }
 
@@ -684,7 +968,24 @@ __global__ void __launch_bounds__(512) k_exchange_wide(LaunchArgs a) {
     exchange_body<J, BOX, MIXED>(a);
 }
 
-size_t exchange_smem_bytes(int threads) { return (size_t)(4 * CH + threads + 4) * sizeof(double); }
+// One workgroup per system.
+template <bool BOX>
+__global__ void __launch_bounds__(256) k_finalize(LaunchArgs a) {
+    __shared__ double red[256];
+    const int si = blockIdx.x;
+    finalize<BOX>(a, a.sys[si], si, red);
+}
+
+hipError_t launch_finalize(const LaunchArgs &a, int S, hipStream_t st) {
+    if (S <= 0) return hipSuccess;
+    if (a.box > 0)
+        hipLaunchKernelGGL(k_finalize<true>, dim3(S), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_finalize<false>, dim3(S), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+size_t exchange_smem_bytes(int threads) { return (size_t)(LDS_RED + threads) * sizeof(double); }
 
 template <bool BOX, bool MIXED>
 static hipError_t launch_j(const LaunchArgs &a, int nitems, int threads, int per_thread, hipStream_t st) {
@@ -848,7 +1149,7 @@ __global__ void k_debug_table(LaunchArgs a, int si, int what, double *dst) {
         const int r = l < N - 1 ? l + 1 : l;
         double p;
         int nr;
-        exp2x(fma(sd.kappa, q2(l, u), -sd.kappa * q2(l, r)), p, nr);
+        exp2x(fmax(fma(sd.kappa, q2(l, u), -sd.kappa * q2(l, r)), XLO), p, nr);
         dst[idx] = ldexp(zfm[u] * p * zbm[l + 2] * nInv / (double)(l + 1),
                          (int)zfe[u] + nr + (int)zbe[l + 2] - ne);
     } else {
