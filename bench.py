@@ -31,11 +31,12 @@ METRIC = "exchange E+F evals/sec at N=1024,P=32 (batched vs plain, 1 GPU)"
 N_HEAD, P_HEAD, BETA = 1024, 32, 1.0
 PEAK_FP64 = 78.6e12  # MI355X FP64 vector peak: 256 CU * 4 SIMD * 16 lanes * 2 flop * 2.4 GHz
 # Algorithmic FP64 flops of one term of one recursion: spring length |d|^2
-# (3 sub + 3 mul + 2 add), exponent (mul + add), the exponential counted as
-# its degree-11 polynomial plus range reduction (11 FMA = 22 flops, + 2),
-# Boltzmann-weight accumulation (mul + add) and the weighted displacement
-# (3 mul + 3 add).  Two recursions of M = N(N+1)/2 terms per evaluation.
-FLOPS_PER_TERM = 8 + 2 + 24 + 2 + 6
+# (3 sub + 3 mul + 2 add), exponent (mul + add), the exponential 2^x to full
+# double accuracy (range reduction 2 + the lowest-degree minimax polynomial
+# that adds no error, degree 10 = 10 FMA = 20), Boltzmann-weight
+# accumulation (mul + add) and the weighted displacement (3 mul + 3 add).
+# Two recursions of M = N(N+1)/2 terms per evaluation.
+FLOPS_PER_TERM = 8 + 2 + 22 + 2 + 6
 
 
 def flops_per_eval(N: int) -> float:

@@ -79,22 +79,38 @@ bool pow2_threads(int t) { return t == 64 || t == 128 || t == 256 || t == 512 ||
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
-// Automatic launch shape.  One system: latency first -- the widest
-// workgroup (most waves to hide FP64 latency) holding the system with 1 or 2
-// particles per thread.  Several systems: throughput first -- 4 particles per
-// thread (more independent accumulators per lane) in the smallest workgroup
-// that holds the largest system.  Above 2048 particles: 8 per thread in
-// 512-thread workgroups (register budget).
+// Automatic launch shape.  The recursion workgroups of the batch (two per
+// system) should bring about 16 waves to every one of the 256 CUs: take the
+// most particles per thread (fewest threads, more independent rows per lane)
+// that still reaches 4096 recursion waves, else the widest workgroup that
+// holds the largest system with one particle per thread.  Per-thread rows
+// stay at 1, 2 or 4 (4 needs the 512-thread kernel); above 2048 particles
+// only 512 threads x 8 rows fit the register budget.
 void auto_tuning(int64_t Nmax, int S, int &threads, int &per) {
     if (Nmax > 2048) {
         threads = 512;
         per = 8;
         return;
     }
-    per = S == 1 ? (Nmax > 1024 ? 2 : 1) : 4;
-    int64_t t = 64;
-    while (t * per < Nmax) t *= 2;
-    threads = (int)t;
+    auto width = [&](int p) {
+        int64_t t = 64;
+        while (t * p < Nmax) t *= 2;
+        return t;
+    };
+    threads = (int)width(1);
+    per = 1;
+    if (threads > 1024) { // 1025..2048 particles
+        threads = 1024;
+        per = 2;
+    }
+    for (int p : {2, 4}) {
+        const int64_t t = width(p);
+        if (p == 4 && t > 512) continue;
+        if (2 * (int64_t)S * (t / 64) >= 4096) {
+            threads = (int)t;
+            per = p;
+        }
+    }
 }
 
 void free_tables(pimdb_t h) {
