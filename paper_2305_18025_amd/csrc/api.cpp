@@ -80,12 +80,13 @@ bool pow2_threads(int t) { return t == 64 || t == 128 || t == 256 || t == 512 ||
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 // Automatic launch shape.  The recursion workgroups of the batch (two per
-// system) should bring about 16 waves to every one of the 256 CUs: take the
-// most particles per thread (fewest threads, more independent rows per lane)
-// that still reaches 4096 recursion waves, else the widest workgroup that
-// holds the largest system with one particle per thread.  Per-thread rows
-// stay at 1, 2 or 4 (4 needs the 512-thread kernel); above 2048 particles
-// only 512 threads x 8 rows fit the register budget.
+// system) should bring about 16 waves to every one of the 256 CUs: two
+// particles per thread (more independent rows per lane) when that still
+// reaches 4096 recursion waves, else the widest workgroup that holds the
+// largest system with one particle per thread.  (Four rows per thread, in
+// the 512-thread kernel with 3 waves per SIMD, measured slower than two at
+// every batch size.)  Above 2048 particles only 512 threads x 8 rows fit
+// the register budget.
 void auto_tuning(int64_t Nmax, int S, int &threads, int &per) {
     if (Nmax > 2048) {
         threads = 512;
@@ -103,13 +104,10 @@ void auto_tuning(int64_t Nmax, int S, int &threads, int &per) {
         threads = 1024;
         per = 2;
     }
-    for (int p : {2, 4}) {
-        const int64_t t = width(p);
-        if (p == 4 && t > 512) continue;
-        if (2 * (int64_t)S * (t / 64) >= 4096) {
-            threads = (int)t;
-            per = p;
-        }
+    const int64_t t2 = width(2);
+    if (2 * (int64_t)S * (t2 / 64) >= 4096) {
+        threads = (int)t2;
+        per = 2;
     }
 }
 

@@ -148,6 +148,16 @@ __device__ __forceinline__ void set_flag(int32_t *flags, int bits) {
 // The backward recursion is the mirror image (blocks descending, rows
 // q <= s, terms (Z_b[l+1]/l) K(q+1, l)).
 //
+// Open boundaries in FP64 (DOT): with coordinates taken relative to a
+// per-system origin, kappa |a - b|^2 + h = (kappa |a|^2 + h) + kappa |b|^2
+// - 2 kappa a.b, so a term's exponent is one add and three FMAs with
+// per-row and per-step constants, and the weighted displacements are
+// recovered from the weighted step points: sum t (a - b) = a sum t - sum t b.
+// The expansion's rounding is about kappa eps |extent|^2 in the exponent
+// (1e-12 relative for a cube of side 10).  Periodic systems (the minimum
+// image is per pair) and the mixed mode (FP32 pair lengths) keep the direct
+// form.
+//
 // Exponent bookkeeping: an accumulator (A, e) stands for A 2^e; a term
 // t 2^te is added as A += t 2^(te - e) while te - e <= RENORM, so A stays
 // below 2^(RENORM + 13) and terms more than 2^1074 below A underflow
@@ -159,9 +169,12 @@ constexpr int KSPLIT = 4;   // waves that share the previous block's terms for t
 constexpr int KTRI = BK * (BK + 1) / 2;
 
 // LDS map (doubles):
-//   [L_STG, +3*8*BK)   ring of 3 staged blocks, per particle
-//                      {x1, y1, z1, xP, yP, zP, h, -}: bead-1 and bead-P
-//                      points and h = -kappa |r^P - r_ref^1|^2
+//   [L_STG, +3*10*BK)  ring of 3 staged blocks, per particle
+//                      {x1, y1, z1, xP, yP, zP, h, Df, Db, -}: bead-1 and
+//                      bead-P points (relative to the origin in the dot
+//                      form), h = -kappa |r^P - r_ref^1|^2, and the dot
+//                      form's step constants Df = kappa |r^1|^2,
+//                      Db = kappa |r^P|^2 + h
 //   [L_ZM, +3*BK)      ring of 3 blocks of broadcast mantissas, per step
 //   [L_ZE, +3*BK/2)    matching exponents (ints)
 //   [L_KP, +KTRI)      the diagonal block's exponentials: mantissas
@@ -170,7 +183,8 @@ constexpr int KTRI = BK * (BK + 1) / 2;
 //   [L_PE, +KSPLIT*BK/2)  their exponents (ints)
 //   [LDS_RED, +T)      block reduction scratch
 constexpr int L_STG = 0;
-constexpr int L_ZM = 3 * 8 * BK;
+constexpr int STG = 10; // doubles per staged particle
+constexpr int L_ZM = 3 * STG * BK;
 constexpr int L_ZE = L_ZM + 3 * BK;
 constexpr int L_KP = L_ZE + 3 * BK / 2;
 constexpr int L_KN = L_KP + KTRI;
@@ -178,7 +192,7 @@ constexpr int L_PA = L_KN + KTRI / 2 + 1;
 constexpr int L_PE = L_PA + KSPLIT * 4 * BK;
 constexpr int LDS_RED = L_PE + KSPLIT * BK / 2;
 
-__device__ __forceinline__ double *stg_block(double *sm, int b) { return sm + L_STG + (b % 3) * 8 * BK; }
+__device__ __forceinline__ double *stg_block(double *sm, int b) { return sm + L_STG + (b % 3) * STG * BK; }
 __device__ __forceinline__ double *zm_block(double *sm, int b) { return sm + L_ZM + (b % 3) * BK; }
 __device__ __forceinline__ int *ze_block(double *sm, int b) { return (int *)(sm + L_ZE) + (b % 3) * BK; }
 __device__ __forceinline__ int *kn_base(double *sm) { return (int *)(sm + L_KN); }
@@ -270,8 +284,11 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Accumulator rows of one thread.  Forward: (px, py, pz) = r_q^P and
-// hl = h_q; backward: (px, py, pz) = r_q^1.
+// Accumulator rows of one thread.  Direct form: (px, py, pz) = r_q^P and
+// hl = h_q (forward) or (px, py, pz) = r_q^1 (backward).  Dot form:
+// (px, py, pz) = -2 kappa times that point, hl = kappa |point|^2 (+ h_q
+// forward).  The accumulator's W holds sum t d (direct) or sum t b over the
+// step points b (dot).
 template <int JJ>
 struct Rows {
     double px[JJ], py[JJ], pz[JJ], hl[JJ];
@@ -284,16 +301,18 @@ struct RecCtx {
     size_t NN;
     int N, T, t, W, nblk;
     double kap, box, ib;
+    double ox, oy, oz; // origin of the dot form (bead 1 of particle 0)
 };
 
 // Staged data of one particle.
 struct Stage {
-    double x1, y1, z1, xP, yP, zP, h;
+    double x1, y1, z1, xP, yP, zP, h, Df, Db;
 };
 
 template <bool BOX, bool MIXED>
 __device__ __forceinline__ Stage stage_load(const RecCtx &c, int b, bool &bad) {
-    Stage g{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    constexpr bool DOT = !BOX && !MIXED;
+    Stage g{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const int l = b * BK + (c.t & 63);
     if (l < c.N) {
         const size_t NN = c.NN;
@@ -308,12 +327,22 @@ __device__ __forceinline__ Stage stage_load(const RecCtx &c, int b, bool &bad) {
                                      mimg<BOX>(g.yP - c.b1[NN + r], c.box, c.ib),
                                      mimg<BOX>(g.zP - c.b1[2 * NN + r], c.box, c.ib));
         bad |= !(g.h <= XHI);
+        if (DOT) {
+            g.x1 -= c.ox;
+            g.y1 -= c.oy;
+            g.z1 -= c.oz;
+            g.xP -= c.ox;
+            g.yP -= c.oy;
+            g.zP -= c.oz;
+            g.Df = c.kap * (g.x1 * g.x1 + g.y1 * g.y1 + g.z1 * g.z1);
+            g.Db = fma(c.kap, g.xP * g.xP + g.yP * g.yP + g.zP * g.zP, g.h);
+        }
     }
     return g;
 }
 
 __device__ __forceinline__ void stage_store(const RecCtx &c, int b, const Stage &g) {
-    double *S = stg_block(c.sm, b) + 8 * (c.t & 63);
+    double *S = stg_block(c.sm, b) + STG * (c.t & 63);
     S[0] = g.x1;
     S[1] = g.y1;
     S[2] = g.z1;
@@ -321,17 +350,30 @@ __device__ __forceinline__ void stage_store(const RecCtx &c, int b, const Stage 
     S[4] = g.yP;
     S[5] = g.zP;
     S[6] = g.h;
+    S[7] = g.Df;
+    S[8] = g.Db;
 }
 
-// The coming term's step data: forward the bead-1 point of u, backward the
-// bead-P point of l and h_l.
-template <bool FWD>
+// A step's data: forward the bead-1 point of u, backward the bead-P point
+// of l; h is h_l (direct form, backward), the step constant Df or Db (dot
+// form), else 0.
+template <bool FWD, bool DOT>
 __device__ __forceinline__ void step_point(const double *S, int i, double &x, double &y, double &z, double &h) {
-    const double *u = S + 8 * i + (FWD ? 0 : 3);
+    const double *u = S + STG * i + (FWD ? 0 : 3);
     x = u[0];
     y = u[1];
     z = u[2];
-    h = FWD ? 0.0 : u[3];
+    h = DOT ? (FWD ? u[7] : u[5]) : (FWD ? 0.0 : u[3]);
+}
+
+// Per-row constants of the dot form for the point (x, y, z) (origin
+// relative) with h (forward) or 0 (backward).
+__device__ __forceinline__ void dot_row(double kap, double x, double y, double z, double h, double &ax, double &ay,
+                                        double &az, double &cq) {
+    ax = -2.0 * kap * x;
+    ay = -2.0 * kap * y;
+    az = -2.0 * kap * z;
+    cq = fma(kap, x * x + y * y + z * z, h);
 }
 
 // Terms of one step for rows [LO, HI), formed in lockstep (each stage of
@@ -348,23 +390,36 @@ __device__ __forceinline__ void panel_step(Rows<JJ> &R, const RecCtx &c, double 
         panel_step<FWD, LO + GM, HI, JJ, BOX, MIXED, WSUM>(R, c, zm, ze, ux, uy, uz, uh);
     } else if constexpr (HI > LO) {
         constexpr int G = HI - LO;
+        constexpr bool DOT = !BOX && !MIXED;
         double x[G], r[G], f[G], p[G], dx[G], dy[G], dz[G];
         int k[G];
+        if (DOT) { // exponent from the row and step constants; W sums t * (step point)
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int j = LO + g;
-            if (FWD) {
-                dx[g] = mimg<BOX>(R.px[j] - ux, c.box, c.ib);
-                dy[g] = mimg<BOX>(R.py[j] - uy, c.box, c.ib);
-                dz[g] = mimg<BOX>(R.pz[j] - uz, c.box, c.ib);
-            } else {
-                dx[g] = mimg<BOX>(ux - R.px[j], c.box, c.ib);
-                dy[g] = mimg<BOX>(uy - R.py[j], c.box, c.ib);
-                dz[g] = mimg<BOX>(uz - R.pz[j], c.box, c.ib);
+            for (int g = 0; g < G; ++g) {
+                const int j = LO + g;
+                x[g] = fma(R.px[j], ux, fma(R.py[j], uy, fma(R.pz[j], uz, R.hl[j] + uh)));
+                dx[g] = ux;
+                dy[g] = uy;
+                dz[g] = uz;
             }
-        }
+        } else {
 #pragma unroll
-        for (int g = 0; g < G; ++g) x[g] = fma(c.kap, sqlen<MIXED>(dx[g], dy[g], dz[g]), FWD ? R.hl[LO + g] : uh);
+            for (int g = 0; g < G; ++g) {
+                const int j = LO + g;
+                if (FWD) {
+                    dx[g] = mimg<BOX>(R.px[j] - ux, c.box, c.ib);
+                    dy[g] = mimg<BOX>(R.py[j] - uy, c.box, c.ib);
+                    dz[g] = mimg<BOX>(R.pz[j] - uz, c.box, c.ib);
+                } else {
+                    dx[g] = mimg<BOX>(ux - R.px[j], c.box, c.ib);
+                    dy[g] = mimg<BOX>(uy - R.py[j], c.box, c.ib);
+                    dz[g] = mimg<BOX>(uz - R.pz[j], c.box, c.ib);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                x[g] = fma(c.kap, sqlen<MIXED>(dx[g], dy[g], dz[g]), FWD ? R.hl[LO + g] : uh);
+        }
 #pragma unroll
         for (int g = 0; g < G; ++g) r[g] = rint(x[g]);
 #pragma unroll
@@ -392,34 +447,37 @@ __device__ __forceinline__ void panel_step(Rows<JJ> &R, const RecCtx &c, double 
     }
 }
 
-// Panel: rows [LO, HI) add the terms of the steps of block blk.
+// Panel: rows [LO, HI) add the terms of the steps of block blk.  Steps go
+// in pairs with two alternating sets of step values, each read one step
+// ahead, so no values are copied between iterations.
 template <bool FWD, int LO, int HI, int JJ, bool BOX, bool MIXED, bool WSUM>
 __device__ __forceinline__ void panel(Rows<JJ> &R, const RecCtx &c, int blk) {
     if constexpr (HI > LO) {
+        constexpr bool DOT = !BOX && !MIXED;
         const int nst = min(BK, c.N - blk * BK);
         const double *S = stg_block(c.sm, blk);
         const double *Z = zm_block(c.sm, blk);
         const int *E = ze_block(c.sm, blk);
-        int i = FWD ? 0 : nst - 1;
-        double ux, uy, uz, uh;
-        step_point<FWD>(S, i, ux, uy, uz, uh);
-        double zm = Z[i];
-        int ze = E[i];
-        for (int n = 0; n < nst; ++n) {
-            // next step's values are read before this step's arithmetic
-            const int i2 = FWD ? min(i + 1, BK - 1) : max(i - 1, 0);
-            double vx, vy, vz, vh;
-            step_point<FWD>(S, i2, vx, vy, vz, vh);
-            const double zm2 = Z[i2];
-            const int ze2 = E[i2];
-            panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM>(R, c, zm, ze, ux, uy, uz, uh);
-            ux = vx;
-            uy = vy;
-            uz = vz;
-            uh = vh;
-            zm = zm2;
-            ze = ze2;
-            i = i2;
+        auto at = [&](int n) { return FWD ? min(n, BK - 1) : max(nst - 1 - n, 0); };
+        double ax, ay, az, ah, bx, by, bz, bh, za, zb;
+        int ea, eb;
+        int i = at(0);
+        step_point<FWD, DOT>(S, i, ax, ay, az, ah);
+        za = Z[i];
+        ea = E[i];
+        for (int n = 0; n < nst; n += 2) {
+            i = at(n + 1);
+            step_point<FWD, DOT>(S, i, bx, by, bz, bh);
+            zb = Z[i];
+            eb = E[i];
+            panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM>(R, c, za, ea, ax, ay, az, ah);
+            if (n + 1 < nst) {
+                i = at(n + 2);
+                step_point<FWD, DOT>(S, i, ax, ay, az, ah);
+                za = Z[i];
+                ea = E[i];
+                panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM>(R, c, zb, eb, bx, by, bz, bh);
+            }
         }
     }
 }
@@ -431,14 +489,14 @@ __device__ __forceinline__ void diag_terms(const RecCtx &c, int k) {
     const int lane = c.t & 63, w = c.t >> 6;
     const int nst = min(BK, c.N - k * BK);
     const double *S = stg_block(c.sm, k);
-    const double *me = S + 8 * lane;
+    const double *me = S + STG * lane;
     double *KP = c.sm + L_KP;
     int *KN = kn_base(c.sm);
     for (int is = w; is < nst; is += c.W) {
         const bool valid = FWD ? lane >= is : lane <= is;
         double ux, uy, uz, uh, p, dx, dy, dz;
         int n;
-        step_point<FWD>(S, is, ux, uy, uz, uh);
+        step_point<FWD, false>(S, is, ux, uy, uz, uh);
         if (FWD)
             kterm<BOX, MIXED>(me[3], me[4], me[5], ux, uy, uz, me[6], c.kap, c.box, c.ib, p, n, dx, dy, dz);
         else
@@ -458,7 +516,7 @@ __device__ __forceinline__ void diag_partial(const RecCtx &c, int k, int prev) {
     const int lane = c.t & 63, w = c.t >> 6;
     const int ns = min(KSPLIT, c.W);
     if (w >= ns) return;
-    const double *me = stg_block(c.sm, k) + 8 * lane;
+    const double *me = stg_block(c.sm, k) + STG * lane;
     Rows<1> R;
     if (FWD) {
         R.px[0] = me[3];
@@ -471,6 +529,7 @@ __device__ __forceinline__ void diag_partial(const RecCtx &c, int k, int prev) {
         R.pz[0] = me[2];
         R.hl[0] = 0.0;
     }
+    if (!BOX && !MIXED) dot_row(c.kap, R.px[0], R.py[0], R.pz[0], R.hl[0], R.px[0], R.py[0], R.pz[0], R.hl[0]);
     R.a[0] = Acc{0.0, 0.0, 0.0, 0.0, EMIN};
     const int nst = min(BK, c.N - prev * BK); // previous block: full except the backward top
     const int i0 = (nst * w) / ns, i1 = (nst * (w + 1)) / ns;
@@ -480,7 +539,7 @@ __device__ __forceinline__ void diag_partial(const RecCtx &c, int k, int prev) {
     for (int n = i0; n < i1; ++n) {
         const int i = FWD ? n : nst - 1 - n;
         double ux, uy, uz, uh;
-        step_point<FWD>(S, i, ux, uy, uz, uh);
+        step_point<FWD, !BOX && !MIXED>(S, i, ux, uy, uz, uh);
         panel_step<FWD, 0, 1, 1, BOX, MIXED, WSUM>(R, c, Z[i], E[i], ux, uy, uz, uh);
     }
     double *PA = c.sm + L_PA + w * 4 * BK + lane;
@@ -525,8 +584,12 @@ __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bo
         double dx = 0.0, dy = 0.0, dz = 0.0;
         if (WSUM) {
             double ux, uy, uz, uh;
-            step_point<FWD>(S, is, ux, uy, uz, uh);
-            if (FWD) {
+            step_point<FWD, !BOX && !MIXED>(S, is, ux, uy, uz, uh);
+            if (!BOX && !MIXED) {
+                dx = ux;
+                dy = uy;
+                dz = uz;
+            } else if (FWD) {
                 dx = mimg<BOX>(R.px[j] - ux, c.box, c.ib);
                 dy = mimg<BOX>(R.py[j] - uy, c.box, c.ib);
                 dz = mimg<BOX>(R.pz[j] - uz, c.box, c.ib);
@@ -563,9 +626,17 @@ __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bo
         }
         if (WSUM) {
             const double ia = 1.0 / r.A;
-            r_out[q] = r.Wx * ia;
-            r_out[NN + q] = r.Wy * ia;
-            r_out[2 * NN + q] = r.Wz * ia;
+            double mx = r.Wx * ia, my = r.Wy * ia, mz2 = r.Wz * ia;
+            if (!BOX && !MIXED) { // from the weighted mean step point
+                const double *me = S + STG * lane + (FWD ? 3 : 0);
+                const double sg = FWD ? -1.0 : 1.0;
+                mx = fma(sg, mx, FWD ? me[0] : -me[0]);
+                my = fma(sg, my, FWD ? me[1] : -me[1]);
+                mz2 = fma(sg, mz2, FWD ? me[2] : -me[2]);
+            }
+            r_out[q] = mx;
+            r_out[NN + q] = my;
+            r_out[2 * NN + q] = mz2;
         }
     }
 }
@@ -656,6 +727,9 @@ __device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDes
                 R.py[j] = c.b1[NN + q];
                 R.pz[j] = c.b1[2 * NN + q];
             }
+            if (!BOX && !MIXED)
+                dot_row(c.kap, R.px[j] - c.ox, R.py[j] - c.oy, R.pz[j] - c.oz, R.hl[j], R.px[j], R.py[j], R.pz[j],
+                        R.hl[j]);
         }
         R.a[j] = Acc{0.0, 0.0, 0.0, 0.0, EMIN};
     }
@@ -738,6 +812,9 @@ __device__ __forceinline__ void recursion_role(const LaunchArgs &a, const SysDes
     c.kap = sd.kappa;
     c.box = a.box;
     c.ib = a.inv_box;
+    c.ox = c.b1[0];
+    c.oy = c.b1[c.NN];
+    c.oz = c.b1[2 * c.NN];
     const int jj = (sd.N + c.T - 1) / c.T;
     rec_dispatch<1, J, FWD, BOX, MIXED, WSUM>(a, sd, c, jj);
 }
