@@ -482,27 +482,40 @@ __device__ __forceinline__ void panel(Rows<JJ> &R, const RecCtx &c, int blk) {
     }
 }
 
-// Phase A1: exponentials of block k's triangle into LDS.  Wave w takes the
-// steps i_s = w, w + W, ...; lane i the accumulator 64 k + i.
+// Phase A1: exponentials of block k's triangle into LDS, 2080 entries in 33
+// folded rows of 64 lanes: work row wr < 32 takes (wr, c) for lanes c >= wr
+// and (63 - wr, 63 - c) for c < wr; work row 32 takes the diagonal entries
+// of rows 32..63.  (Coordinates of the forward triangle s <= q; the
+// backward one is its mirror image.)  Wave w takes work rows w, w + W, ...
 template <bool FWD, bool BOX, bool MIXED>
 __device__ __forceinline__ void diag_terms(const RecCtx &c, int k) {
     const int lane = c.t & 63, w = c.t >> 6;
     const int nst = min(BK, c.N - k * BK);
     const double *S = stg_block(c.sm, k);
-    const double *me = S + STG * lane;
     double *KP = c.sm + L_KP;
     int *KN = kn_base(c.sm);
-    for (int is = w; is < nst; is += c.W) {
-        const bool valid = FWD ? lane >= is : lane <= is;
-        double ux, uy, uz, uh, p, dx, dy, dz;
-        int n;
-        step_point<FWD, false>(S, is, ux, uy, uz, uh);
-        if (FWD)
-            kterm<BOX, MIXED>(me[3], me[4], me[5], ux, uy, uz, me[6], c.kap, c.box, c.ib, p, n, dx, dy, dz);
-        else
-            kterm<BOX, MIXED>(ux, uy, uz, me[0], me[1], me[2], uh, c.kap, c.box, c.ib, p, n, dx, dy, dz);
-        if (valid) {
-            const int ix = tri_index<FWD>(is, lane);
+    for (int wr = w; wr <= BK / 2; wr += c.W) {
+        int r, q; // forward-triangle row (step) and column (accumulator)
+        bool ok = true;
+        if (wr < BK / 2) {
+            r = lane >= wr ? wr : BK - 1 - wr;
+            q = lane >= wr ? lane : BK - 1 - lane;
+        } else {
+            ok = lane < BK / 2;
+            r = q = BK - 1 - lane;
+        }
+        const int is = FWD ? r : BK - 1 - r;  // step
+        const int iq = FWD ? q : BK - 1 - q;  // accumulator
+        if (ok && is < nst) {
+            const double *me = S + STG * iq;
+            double ux, uy, uz, uh, p, dx, dy, dz;
+            int n;
+            step_point<FWD, false>(S, is, ux, uy, uz, uh);
+            if (FWD)
+                kterm<BOX, MIXED>(me[3], me[4], me[5], ux, uy, uz, me[6], c.kap, c.box, c.ib, p, n, dx, dy, dz);
+            else
+                kterm<BOX, MIXED>(ux, uy, uz, me[0], me[1], me[2], uh, c.kap, c.box, c.ib, p, n, dx, dy, dz);
+            const int ix = tri_index<FWD>(is, iq);
             KP[ix] = p;
             KN[ix] = n;
         }
@@ -575,38 +588,59 @@ __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bo
     const int first = FWD ? 0 : nst - 1;
     double zm = zm_block(c.sm, k)[first];
     int ze = ze_block(c.sm, k)[first];
-    for (int i = 0; i < nst; ++i) {
-        const int is = FWD ? i : nst - 1 - i;
+    // a step's own values (its term for this lane and its point), read one
+    // step ahead so the LDS latency stays off the serial chain
+    struct DStep {
+        double p, x, y, z;
+        int n;
+    };
+    auto fetch = [&](int i) {
+        const int is = FWD ? min(i, nst - 1) : max(nst - 1 - i, 0);
         const bool live = FWD ? lane >= is : lane <= is;
         const int ix = tri_index<FWD>(is, live ? lane : is);
-        const double p = KP[ix];
-        const int n = KN[ix];
+        DStep d;
+        d.p = KP[ix];
+        d.n = KN[ix];
+        double uh;
+        step_point<FWD, !BOX && !MIXED>(S, is, d.x, d.y, d.z, uh);
+        return d;
+    };
+    auto step = [&](int i, const DStep &d) {
+        const int is = FWD ? i : nst - 1 - i;
+        const bool live = FWD ? lane >= is : lane <= is;
         double dx = 0.0, dy = 0.0, dz = 0.0;
         if (WSUM) {
-            double ux, uy, uz, uh;
-            step_point<FWD, !BOX && !MIXED>(S, is, ux, uy, uz, uh);
             if (!BOX && !MIXED) {
-                dx = ux;
-                dy = uy;
-                dz = uz;
+                dx = d.x;
+                dy = d.y;
+                dz = d.z;
             } else if (FWD) {
-                dx = mimg<BOX>(R.px[j] - ux, c.box, c.ib);
-                dy = mimg<BOX>(R.py[j] - uy, c.box, c.ib);
-                dz = mimg<BOX>(R.pz[j] - uz, c.box, c.ib);
+                dx = mimg<BOX>(R.px[j] - d.x, c.box, c.ib);
+                dy = mimg<BOX>(R.py[j] - d.y, c.box, c.ib);
+                dz = mimg<BOX>(R.pz[j] - d.z, c.box, c.ib);
             } else {
-                dx = mimg<BOX>(ux - R.px[j], c.box, c.ib);
-                dy = mimg<BOX>(uy - R.py[j], c.box, c.ib);
-                dz = mimg<BOX>(uz - R.pz[j], c.box, c.ib);
+                dx = mimg<BOX>(d.x - R.px[j], c.box, c.ib);
+                dy = mimg<BOX>(d.y - R.py[j], c.box, c.ib);
+                dz = mimg<BOX>(d.z - R.pz[j], c.box, c.ib);
             }
         }
-        const int te = live ? add_sat(ze, n) : EMASK;
+        const int te = live ? add_sat(ze, d.n) : EMASK;
         int kk = sub_sat(te, r.e);
         if (kk > RENORM) kk = acc_shift<WSUM>(r, te);
-        acc_add<WSUM>(r, zm * p, kk, dx, dy, dz);
+        acc_add<WSUM>(r, zm * d.p, kk, dx, dy, dz);
         // the owner (lane is) is complete: broadcast its scaled sum
         const double zz = r.A * ivd;
         zm = readlane_f64(__builtin_amdgcn_frexp_mant(zz), is);
         ze = __builtin_amdgcn_readlane(r.e + __builtin_amdgcn_frexp_exp(zz), is);
+    };
+    DStep da = fetch(0), db;
+    for (int i = 0; i < nst; i += 2) {
+        db = fetch(i + 1);
+        step(i, da);
+        if (i + 1 < nst) {
+            da = fetch(i + 2);
+            step(i + 1, db);
+        }
     }
     if (q < N) {
         const double zz = r.A * ivd;
