@@ -169,14 +169,17 @@ constexpr int KSPLIT = 4;   // waves that share the previous block's terms for t
 constexpr int KTRI = BK * (BK + 1) / 2;
 
 // LDS map (doubles):
-//   [L_STG, +3*10*BK)  ring of 3 staged blocks, per particle
+//   [L_STG, +3*10*BS)  ring of 3 staged blocks, per particle
 //                      {x1, y1, z1, xP, yP, zP, h, Df, Db, -}: bead-1 and
 //                      bead-P points (relative to the origin in the dot
 //                      form), h = -kappa |r^P - r_ref^1|^2, and the dot
 //                      form's step constants Df = kappa |r^1|^2,
 //                      Db = kappa |r^P|^2 + h
-//   [L_ZM, +3*BK)      ring of 3 blocks of broadcast mantissas, per step
-//   [L_ZE, +3*BK/2)    matching exponents (ints)
+//   [L_ZM, +3*BS)      ring of 3 blocks of broadcast mantissas, per step
+//   [L_ZE, +3*BS/2)    matching exponents (ints)
+// Ring slots hold BS = BK + 2 entries: one guard entry on each side, so a
+// panel may read one step past either end of its block without a bounds
+// clamp (the guard values are never used).
 //   [L_KP, +KTRI)      the diagonal block's exponentials: mantissas
 //   [L_KN, +KTRI/2)    and exponents (ints), packed triangle
 //   [L_PA, +KSPLIT*4*BK)  partial sums {A, Wx, Wy, Wz} per wave and lane
@@ -184,17 +187,18 @@ constexpr int KTRI = BK * (BK + 1) / 2;
 //   [LDS_RED, +T)      block reduction scratch
 constexpr int L_STG = 0;
 constexpr int STG = 10; // doubles per staged particle
-constexpr int L_ZM = 3 * STG * BK;
-constexpr int L_ZE = L_ZM + 3 * BK;
-constexpr int L_KP = L_ZE + 3 * BK / 2;
+constexpr int BS = BK + 2;
+constexpr int L_ZM = L_STG + 3 * STG * BS;
+constexpr int L_ZE = L_ZM + 3 * BS;
+constexpr int L_KP = L_ZE + 3 * BS / 2;
 constexpr int L_KN = L_KP + KTRI;
 constexpr int L_PA = L_KN + KTRI / 2 + 1;
 constexpr int L_PE = L_PA + KSPLIT * 4 * BK;
 constexpr int LDS_RED = L_PE + KSPLIT * BK / 2;
 
-__device__ __forceinline__ double *stg_block(double *sm, int b) { return sm + L_STG + (b % 3) * STG * BK; }
-__device__ __forceinline__ double *zm_block(double *sm, int b) { return sm + L_ZM + (b % 3) * BK; }
-__device__ __forceinline__ int *ze_block(double *sm, int b) { return (int *)(sm + L_ZE) + (b % 3) * BK; }
+__device__ __forceinline__ double *stg_block(double *sm, int b) { return sm + L_STG + ((b % 3) * BS + 1) * STG; }
+__device__ __forceinline__ double *zm_block(double *sm, int b) { return sm + L_ZM + (b % 3) * BS + 1; }
+__device__ __forceinline__ int *ze_block(double *sm, int b) { return (int *)(sm + L_ZE) + (b % 3) * BS + 1; }
 __device__ __forceinline__ int *kn_base(double *sm) { return (int *)(sm + L_KN); }
 __device__ __forceinline__ int *pe_base(double *sm) { return (int *)(sm + L_PE); }
 
@@ -458,7 +462,7 @@ __device__ __forceinline__ void panel(Rows<JJ> &R, const RecCtx &c, int blk) {
         const double *S = stg_block(c.sm, blk);
         const double *Z = zm_block(c.sm, blk);
         const int *E = ze_block(c.sm, blk);
-        auto at = [&](int n) { return FWD ? min(n, BK - 1) : max(nst - 1 - n, 0); };
+        auto at = [&](int n) { return FWD ? n : nst - 1 - n; }; // -1 .. BK: guard entries at the ends
         double ax, ay, az, ah, bx, by, bz, bh, za, zb;
         int ea, eb;
         int i = at(0);

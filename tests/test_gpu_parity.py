@@ -232,3 +232,18 @@ def test_chain_configuration_renormalisation(scale):
     F, E = eng.forces(pos)
     assert eng.status() == 0
     _assert_parity(eng, F, E, [s], TOL64)
+
+
+@pytest.mark.parametrize("offset", [0.0, 1.0e3, -3.0e4])
+def test_translated_system(offset):
+    """The exchange potential and forces are translation invariant.  For open
+    boundaries the kernels expand |a - b|^2 around a per-system origin, so a
+    system far from the coordinate origin must keep full accuracy: a cube of
+    side 10 (N=700, P=8) shifted by `offset` along (1, -2, 3)/sqrt(14),
+    against the long-double oracle of the shifted system."""
+    R = cube_system(700, 8, seed=77, side=700 ** (1 / 3))
+    shift = offset * np.array([1.0, -2.0, 3.0]) / np.sqrt(14.0)
+    s = System(R + shift, beta=1.0)
+    eng, pos = _engine([s])
+    F, E = eng.forces(pos)
+    _assert_parity(eng, F, E, [s], TOL64)
