@@ -116,6 +116,74 @@ def accuracy(eng, F, E, R_list, precision="f80", which=(0,)):
     return ee, fe
 
 
+def time_calls(fn, reps):
+    """Average ms of fn() over reps calls, HIP events on the current stream."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def extra_workloads(steps):
+    """The other configurations, measured as context: the 64-system uneven
+    batch (one evaluation and one velocity-Verlet step with the trap, both
+    graph-replayed), the periodic N=4096, P=64 system (evaluation and MD
+    step), and the endpoint-spring table export."""
+    import torch
+    from paper_2305_18025_amd import BosonicExchange, VelocityVerlet, inputs
+    out = {}
+    systems = inputs.config_batch()
+    eng = BosonicExchange([x.N for x in systems], [x.P for x in systems], [x.beta for x in systems],
+                          [x.m for x in systems], [x.omegaP for x in systems], trap=1.0)
+    pos = eng.pack([x.R for x in systems])
+    w, ms, _ = time_graph(eng, pos, steps, 2)
+    vel = eng.pack([inputs.initial_velocities(x.N, x.P, x.beta, x.m, seed=100 + i) for i, x in enumerate(systems)])
+    md = VelocityVerlet(eng, pos.clone(), vel, 0.01)
+    md.capture(steps_per_replay=10)
+    md_ms = time_calls(lambda: md.replay(1), max(2, steps // 10)) / 10
+    out["uneven_batch"] = {"systems": len(systems), "N_range": [min(x.N for x in systems), max(x.N for x in systems)],
+                           "evals_per_s": len(systems) / (ms * 1e-3), "ms_per_launch": ms,
+                           "md_ms_per_step": md_ms, "launch_shape": list(eng.tuning)}
+    del eng, pos, vel, md
+    x = inputs.config_large()
+    eng = BosonicExchange(x.N, x.P, x.beta, x.m, x.omegaP, box=x.box)
+    pos = eng.pack(x.R)
+    F = eng.empty()
+    E = torch.empty(1, dtype=torch.float64, device=eng.device)
+    ms = time_calls(lambda: eng.forces(pos, out=F, energy=E), steps)
+    vel = eng.pack(inputs.initial_velocities(x.N, x.P, x.beta, x.m, seed=55))
+    md = VelocityVerlet(eng, pos.clone(), vel, 0.001)
+    md.capture(steps_per_replay=10)
+    md_ms = time_calls(lambda: md.replay(1), max(2, steps // 10)) / 10
+    out["large_periodic"] = {"N": x.N, "P": x.P, "box": x.box, "ms_per_eval": ms, "evals_per_s": 1e3 / ms,
+                             "ns_per_recursion_step": ms * 1e6 / x.N, "md_ms_per_step": md_ms,
+                             "launch_shape": list(eng.tuning)}
+    # endpoint-spring table s(v,u), u <= v: M values written per call
+    tab = {}
+    for n, s_ in ((N_HEAD, None), (x.N, x)):
+        if s_ is None:
+            e2 = BosonicExchange(n, P_HEAD, BETA)
+            p2 = e2.pack(inputs.gaussian_system(n, P_HEAD, seed=3))
+        else:
+            e2, p2 = eng, pos
+        M = n * (n + 1) // 2
+        for as_float in (False, True):
+            buf = torch.empty(M, dtype=torch.float32 if as_float else torch.float64, device=e2.device)
+            t = time_calls(lambda: e2.endpoint_springs(p2, 0, as_float=as_float, out=buf), steps)
+            nbytes = M * (4 if as_float else 8) + 2 * 3 * n * 8
+            tab["N%d_%s" % (n, "f32" if as_float else "f64")] = {"ms": t, "GB_per_s": nbytes / (t * 1e-3) / 1e9,
+                                                                  "frac_of_8TBs": nbytes / (t * 1e-3) / 8e12}
+    out["endpoint_table"] = tab
+    return out
+
+
 def cpu_baseline(seconds, max_threads=16):
     """The FP64 C oracle (as it stands) on the host cores: independent
     N=1024, P=32 evaluations (energy + forces) in a thread pool for about
@@ -284,8 +352,14 @@ def main():
         for _ in range(args.steps):
             eng.distinguishable(pos, Fd, Ed)
         torch.cuda.synchronize()
-        out["distinguishable"] = {"evals_per_s": B * args.steps / (time.perf_counter() - t0),
-                                  "description": "ring-polymer springs without exchange, same batch"}
+        sec_d = (time.perf_counter() - t0) / args.steps
+        spring_bytes = 2 * pos.numel() * 8  # every bead read and written once
+        out["distinguishable"] = {"evals_per_s": B / sec_d,
+                                  "description": "ring-polymer springs without exchange, same batch",
+                                  "springs_TB_per_s": spring_bytes / sec_d / 1e12,
+                                  "springs_frac_of_8TBs": spring_bytes / sec_d / 8e12}
+        out["plain"]["ns_per_recursion_step"] = sec_plain * 1e9 / N_HEAD
+        out.update(extra_workloads(args.steps))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out))

@@ -165,7 +165,8 @@ __device__ __forceinline__ void set_flag(int32_t *flags, int bits) {
 // first moves the reference: A, W scaled by 2^(e - te), e = te.
 constexpr int BK = 64;
 constexpr int RENORM = 960;
-constexpr int KSPLIT = 4;   // waves that share the previous block's terms for the diagonal rows
+constexpr int KSPLIT = 8;   // most waves that share the previous block's terms for the diagonal rows
+                            // (8 in 16-wave workgroups, else 4)
 constexpr int KTRI = BK * (BK + 1) / 2;
 
 // LDS map (doubles):
@@ -184,7 +185,9 @@ constexpr int KTRI = BK * (BK + 1) / 2;
 //   [L_KN, +KTRI/2)    and exponents (ints), packed triangle
 //   [L_PA, +KSPLIT*4*BK)  partial sums {A, Wx, Wy, Wz} per wave and lane
 //   [L_PE, +KSPLIT*BK/2)  their exponents (ints)
-//   [LDS_RED, +T)      block reduction scratch
+//   [LDS_RED, +T)      block reduction scratch of the spring role (a
+//                      workgroup runs either a recursion or springs, so
+//                      this aliases the recursion regions)
 constexpr int L_STG = 0;
 constexpr int STG = 10; // doubles per staged particle
 constexpr int BS = BK + 2;
@@ -194,7 +197,8 @@ constexpr int L_KP = L_ZE + 3 * BS / 2;
 constexpr int L_KN = L_KP + KTRI;
 constexpr int L_PA = L_KN + KTRI / 2 + 1;
 constexpr int L_PE = L_PA + KSPLIT * 4 * BK;
-constexpr int LDS_RED = L_PE + KSPLIT * BK / 2;
+constexpr int L_END = L_PE + KSPLIT * BK / 2;
+constexpr int LDS_RED = 0;
 
 __device__ __forceinline__ double *stg_block(double *sm, int b) { return sm + L_STG + ((b % 3) * BS + 1) * STG; }
 __device__ __forceinline__ double *zm_block(double *sm, int b) { return sm + L_ZM + (b % 3) * BS + 1; }
@@ -531,7 +535,7 @@ __device__ __forceinline__ void diag_terms(const RecCtx &c, int k) {
 template <bool FWD, bool BOX, bool MIXED, bool WSUM>
 __device__ __forceinline__ void diag_partial(const RecCtx &c, int k, int prev) {
     const int lane = c.t & 63, w = c.t >> 6;
-    const int ns = min(KSPLIT, c.W);
+    const int ns = c.W >= 16 ? KSPLIT : min(KSPLIT / 2, c.W);
     if (w >= ns) return;
     const double *me = stg_block(c.sm, k) + STG * lane;
     Rows<1> R;
@@ -579,7 +583,7 @@ __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bo
     const int nst = min(BK, N - k * BK);
     Acc &r = R.a[j];
     if (has_prev) {
-        const int ns = min(KSPLIT, c.W);
+        const int ns = c.W >= 16 ? KSPLIT : min(KSPLIT / 2, c.W);
         for (int w = 0; w < ns; ++w) {
             const double *PA = c.sm + L_PA + w * 4 * BK + lane;
             acc_merge<WSUM>(r, Acc{PA[0], PA[BK], PA[2 * BK], PA[3 * BK], pe_base(c.sm)[w * BK + lane]});
@@ -1100,7 +1104,7 @@ hipError_t launch_finalize(const LaunchArgs &a, int S, hipStream_t st) {
     return hipGetLastError();
 }
 
-size_t exchange_smem_bytes(int threads) { return (size_t)(LDS_RED + threads) * sizeof(double); }
+size_t exchange_smem_bytes(int threads) { return (size_t)(threads > L_END ? threads : L_END) * sizeof(double); }
 
 template <bool BOX, bool MIXED>
 static hipError_t launch_j(const LaunchArgs &a, int nitems, int threads, int per_thread, hipStream_t st) {
