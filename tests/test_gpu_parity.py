@@ -247,3 +247,21 @@ def test_translated_system(offset):
     eng, pos = _engine([s])
     F, E = eng.forces(pos)
     _assert_parity(eng, F, E, [s], TOL64)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("where", ["first", "middle", "last"])
+def test_far_particle_rescaling(where, precision):
+    """One particle 50 units from a dense cluster: its terms are about
+    2^-57000 below the others, so accumulators that start with it must move
+    their exponent reference when the near terms arrive (forward recursion
+    for the first particle, backward for the last)."""
+    N, P = 300, 6
+    R = gaussian_system(N, P, seed=91, sigma_c=1.0)
+    i = {"first": 0, "middle": N // 2, "last": N - 1}[where]
+    R[i] += np.array([50.0, 0.0, 0.0])
+    s = System(R, beta=1.0)
+    eng, pos = _engine([s], precision=precision)
+    F, E = eng.forces(pos)
+    assert eng.status() == 0
+    _assert_parity(eng, F, E, [s], TOL64 if precision == "fp64" else TOLMIX)
