@@ -56,6 +56,7 @@
 namespace pimdb {
 
 constexpr double LN2 = 0.6931471805599453;
+constexpr double LOG2E = 1.4426950408889634;
 constexpr double XLO = -536870912.0;     // -2^29: lower clamp of an exported term exponent
 constexpr double XHI = 268435456.0;      //  2^28: bound on h = -kappa |d_ref|^2
 constexpr int EMIN = -(1 << 30);         // exponent of an empty accumulator
@@ -178,11 +179,16 @@ constexpr int KTRI = BK * (BK + 1) / 2;
 //                      Db = kappa |r^P|^2 + h
 //   [L_ZM, +3*BS)      ring of 3 blocks of broadcast mantissas, per step
 //   [L_ZE, +3*BS/2)    matching exponents (ints)
+//   [L_ZL, +3*BS)      log2 of the mantissa plus the step's own exponent
+//                      constant (what the panel terms use)
 // Ring slots hold BS = BK + 2 entries: one guard entry on each side, so a
 // panel may read one step past either end of its block without a bounds
 // clamp (the guard values are never used).
-//   [L_KP, +KTRI)      the diagonal block's exponentials: mantissas
-//   [L_KN, +KTRI/2)    and exponents (ints), packed triangle
+//   [L_KP, +KTRI)      the diagonal block's exponentials: mantissas,
+//                      packed triangle (zero-filled once, so reads past a
+//                      row's live part return finite values)
+//   [L_KN, +BK*BK/2)   their exponents (ints), full 64 x 64 rows; entries of
+//                      lanes a step does not reach hold EMASK (filled once)
 //   [L_PA, +KSPLIT*4*BK)  partial sums {A, Wx, Wy, Wz} per wave and lane
 //   [L_PE, +KSPLIT*BK/2)  their exponents (ints)
 //   [LDS_RED, +T)      block reduction scratch of the spring role (a
@@ -193,9 +199,10 @@ constexpr int STG = 10; // doubles per staged particle
 constexpr int BS = BK + 2;
 constexpr int L_ZM = L_STG + 3 * STG * BS;
 constexpr int L_ZE = L_ZM + 3 * BS;
-constexpr int L_KP = L_ZE + 3 * BS / 2;
+constexpr int L_ZL = L_ZE + 3 * BS / 2;
+constexpr int L_KP = L_ZL + 3 * BS;
 constexpr int L_KN = L_KP + KTRI;
-constexpr int L_PA = L_KN + KTRI / 2 + 1;
+constexpr int L_PA = L_KN + BK * BK / 2;
 constexpr int L_PE = L_PA + KSPLIT * 4 * BK;
 constexpr int L_END = L_PE + KSPLIT * BK / 2;
 constexpr int LDS_RED = 0;
@@ -203,6 +210,7 @@ constexpr int LDS_RED = 0;
 __device__ __forceinline__ double *stg_block(double *sm, int b) { return sm + L_STG + ((b % 3) * BS + 1) * STG; }
 __device__ __forceinline__ double *zm_block(double *sm, int b) { return sm + L_ZM + (b % 3) * BS + 1; }
 __device__ __forceinline__ int *ze_block(double *sm, int b) { return (int *)(sm + L_ZE) + (b % 3) * BS + 1; }
+__device__ __forceinline__ double *zl_block(double *sm, int b) { return sm + L_ZL + (b % 3) * BS + 1; }
 __device__ __forceinline__ int *kn_base(double *sm) { return (int *)(sm + L_KN); }
 __device__ __forceinline__ int *pe_base(double *sm) { return (int *)(sm + L_PE); }
 
@@ -263,6 +271,19 @@ __device__ __forceinline__ void acc_merge(Acc &r, const Acc &o) {
         r.Wz = ldexp(r.Wz, a) + ldexp(o.Wz, b);
     }
     r.e = en;
+}
+
+// log2(m) for a mantissa m in [0.5, 1): m is scaled into [1/sqrt 2, sqrt 2)
+// and ln(m) = 2 atanh(s), s = (m - 1) / (m + 1), |s| <= 0.172, summed as the
+// odd series s + s^3/3 + ... + s^21/21 (truncation below 1e-18).
+__device__ __forceinline__ double log2_mant(double m) {
+    const bool lo = m < 0.70710678118654752;
+    const double x = lo ? 2.0 * m : m;
+    const double s = (x - 1.0) / (x + 1.0), s2 = s * s;
+    double p = 1.0 / 21.0;
+#pragma unroll
+    for (int k = 9; k >= 0; --k) p = fma(p, s2, 1.0 / (double)(2 * k + 1));
+    return (2.0 * LOG2E) * (s * p) - (lo ? 1.0 : 0.0);
 }
 
 // 2^x as mantissa p in [0.7, 1.42] and integer exponent n; n saturates for
@@ -374,6 +395,13 @@ __device__ __forceinline__ void step_point(const double *S, int i, double &x, do
     h = DOT ? (FWD ? u[7] : u[5]) : (FWD ? 0.0 : u[3]);
 }
 
+// The exponent constant of the step whose staged record is su: forward 0
+// (direct) or Df (dot); backward h (direct) or Db (dot).
+template <bool FWD, bool DOT>
+__device__ __forceinline__ double step_const(const double *su) {
+    return DOT ? (FWD ? su[7] : su[8]) : (FWD ? 0.0 : su[6]);
+}
+
 // Per-row constants of the dot form for the point (x, y, z) (origin
 // relative) with h (forward) or 0 (backward).
 __device__ __forceinline__ void dot_row(double kap, double x, double y, double z, double h, double &ax, double &ay,
@@ -389,13 +417,13 @@ __device__ __forceinline__ void dot_row(double kap, double x, double y, double z
 // different rows interleave.  With 3 or more rows per thread they go in
 // groups of 2 (register budget: 3 waves per SIMD).
 template <bool FWD, int LO, int HI, int JJ, bool BOX, bool MIXED, bool WSUM>
-__device__ __forceinline__ void panel_step(Rows<JJ> &R, const RecCtx &c, double zm, int ze, double ux, double uy,
-                                           double uz, double uh) {
+__device__ __forceinline__ void panel_step(Rows<JJ> &R, const RecCtx &c, double zl, int ze, double ux, double uy,
+                                           double uz) {
     constexpr int GM = JJ >= 3 ? 2 : 4;
     if constexpr (HI - LO > GM) {
-        panel_step<FWD, LO, LO + GM, JJ, BOX, MIXED, WSUM>(R, c, zm, ze, ux, uy, uz, uh);
+        panel_step<FWD, LO, LO + GM, JJ, BOX, MIXED, WSUM>(R, c, zl, ze, ux, uy, uz);
         __builtin_amdgcn_sched_barrier(0);
-        panel_step<FWD, LO + GM, HI, JJ, BOX, MIXED, WSUM>(R, c, zm, ze, ux, uy, uz, uh);
+        panel_step<FWD, LO + GM, HI, JJ, BOX, MIXED, WSUM>(R, c, zl, ze, ux, uy, uz);
     } else if constexpr (HI > LO) {
         constexpr int G = HI - LO;
         constexpr bool DOT = !BOX && !MIXED;
@@ -405,7 +433,7 @@ __device__ __forceinline__ void panel_step(Rows<JJ> &R, const RecCtx &c, double 
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 const int j = LO + g;
-                x[g] = fma(R.px[j], ux, fma(R.py[j], uy, fma(R.pz[j], uz, R.hl[j] + uh)));
+                x[g] = fma(R.px[j], ux, fma(R.py[j], uy, fma(R.pz[j], uz, R.hl[j] + zl)));
                 dx[g] = ux;
                 dy[g] = uy;
                 dz[g] = uz;
@@ -426,7 +454,7 @@ __device__ __forceinline__ void panel_step(Rows<JJ> &R, const RecCtx &c, double 
             }
 #pragma unroll
             for (int g = 0; g < G; ++g)
-                x[g] = fma(c.kap, sqlen<MIXED>(dx[g], dy[g], dz[g]), FWD ? R.hl[LO + g] : uh);
+                x[g] = fma(c.kap, sqlen<MIXED>(dx[g], dy[g], dz[g]), FWD ? R.hl[LO + g] + zl : zl);
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) r[g] = rint(x[g]);
@@ -451,7 +479,7 @@ __device__ __forceinline__ void panel_step(Rows<JJ> &R, const RecCtx &c, double 
             for (int g = 0; g < G; ++g) k[g] = acc_shift<WSUM>(R.a[LO + g], add_sat(ze, (int)r[g]));
         }
 #pragma unroll
-        for (int g = 0; g < G; ++g) acc_add<WSUM>(R.a[LO + g], zm * p[g], k[g], dx[g], dy[g], dz[g]);
+        for (int g = 0; g < G; ++g) acc_add<WSUM>(R.a[LO + g], p[g], k[g], dx[g], dy[g], dz[g]);
     }
 }
 
@@ -464,7 +492,7 @@ __device__ __forceinline__ void panel(Rows<JJ> &R, const RecCtx &c, int blk) {
         constexpr bool DOT = !BOX && !MIXED;
         const int nst = min(BK, c.N - blk * BK);
         const double *S = stg_block(c.sm, blk);
-        const double *Z = zm_block(c.sm, blk);
+        const double *Z = zl_block(c.sm, blk);
         const int *E = ze_block(c.sm, blk);
         auto at = [&](int n) { return FWD ? n : nst - 1 - n; }; // -1 .. BK: guard entries at the ends
         double ax, ay, az, ah, bx, by, bz, bh, za, zb;
@@ -478,13 +506,13 @@ __device__ __forceinline__ void panel(Rows<JJ> &R, const RecCtx &c, int blk) {
             step_point<FWD, DOT>(S, i, bx, by, bz, bh);
             zb = Z[i];
             eb = E[i];
-            panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM>(R, c, za, ea, ax, ay, az, ah);
+            panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM>(R, c, za, ea, ax, ay, az);
             if (n + 1 < nst) {
                 i = at(n + 2);
                 step_point<FWD, DOT>(S, i, ax, ay, az, ah);
                 za = Z[i];
                 ea = E[i];
-                panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM>(R, c, zb, eb, bx, by, bz, bh);
+                panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM>(R, c, zb, eb, bx, by, bz);
             }
         }
     }
@@ -523,9 +551,8 @@ __device__ __forceinline__ void diag_terms(const RecCtx &c, int k) {
                 kterm<BOX, MIXED>(me[3], me[4], me[5], ux, uy, uz, me[6], c.kap, c.box, c.ib, p, n, dx, dy, dz);
             else
                 kterm<BOX, MIXED>(ux, uy, uz, me[0], me[1], me[2], uh, c.kap, c.box, c.ib, p, n, dx, dy, dz);
-            const int ix = tri_index<FWD>(is, iq);
-            KP[ix] = p;
-            KN[ix] = n;
+            KP[tri_index<FWD>(is, iq)] = p;
+            KN[is * BK + iq] = n;
         }
     }
 }
@@ -555,13 +582,13 @@ __device__ __forceinline__ void diag_partial(const RecCtx &c, int k, int prev) {
     const int nst = min(BK, c.N - prev * BK); // previous block: full except the backward top
     const int i0 = (nst * w) / ns, i1 = (nst * (w + 1)) / ns;
     const double *S = stg_block(c.sm, prev);
-    const double *Z = zm_block(c.sm, prev);
+    const double *Z = zl_block(c.sm, prev);
     const int *E = ze_block(c.sm, prev);
     for (int n = i0; n < i1; ++n) {
         const int i = FWD ? n : nst - 1 - n;
         double ux, uy, uz, uh;
         step_point<FWD, !BOX && !MIXED>(S, i, ux, uy, uz, uh);
-        panel_step<FWD, 0, 1, 1, BOX, MIXED, WSUM>(R, c, Z[i], E[i], ux, uy, uz, uh);
+        panel_step<FWD, 0, 1, 1, BOX, MIXED, WSUM>(R, c, Z[i], E[i], ux, uy, uz);
     }
     double *PA = c.sm + L_PA + w * 4 * BK + lane;
     PA[0] = R.a[0].A;
@@ -575,7 +602,7 @@ __device__ __forceinline__ void diag_partial(const RecCtx &c, int k, int prev) {
 // serially on row j (lane i: accumulator 64 k + i).  Afterwards every lane's
 // row is final: its published value goes to the broadcast ring for the
 // panels and its results to global memory.
-template <bool FWD, int j, int JJ, bool BOX, bool MIXED, bool WSUM>
+template <bool FWD, int j, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR>
 __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bool has_prev, double *zm_out,
                                          double *ze_out, double *r_out) {
     const int lane = c.t & 63, q = k * BK + lane, N = c.N;
@@ -591,63 +618,80 @@ __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bo
     }
     const double ivd = FWD ? 1.0 / (double)(q + 1) : (q > 0 ? 1.0 / (double)q : 0.0);
     const double *S = stg_block(c.sm, k);
-    const double *KP = c.sm + L_KP;
-    const int *KN = kn_base(c.sm);
+    const double *KPl = c.sm + L_KP + lane;
+    const int *KNl = kn_base(c.sm) + lane;
     const int first = FWD ? 0 : nst - 1;
     double zm = zm_block(c.sm, k)[first];
     int ze = ze_block(c.sm, k)[first];
-    // a step's own values (its term for this lane and its point), read one
-    // step ahead so the LDS latency stays off the serial chain
-    struct DStep {
-        double p, x, y, z;
-        int n;
-    };
-    auto fetch = [&](int i) {
-        const int is = FWD ? min(i, nst - 1) : max(nst - 1 - i, 0);
-        const bool live = FWD ? lane >= is : lane <= is;
-        const int ix = tri_index<FWD>(is, live ? lane : is);
-        DStep d;
-        d.p = KP[ix];
-        d.n = KN[ix];
-        double uh;
-        step_point<FWD, !BOX && !MIXED>(S, is, d.x, d.y, d.z, uh);
-        return d;
-    };
-    auto step = [&](int i, const DStep &d) {
-        const int is = FWD ? i : nst - 1 - i;
-        const bool live = FWD ? lane >= is : lane <= is;
+    // One step: every lane adds the term of step is (lanes the step does not
+    // reach read an EMASK exponent and add nothing; their KP reads stay
+    // inside the zero-filled triangle), then the owner (lane is) is complete
+    // and its scaled sum is broadcast.
+    auto step = [&](int is, double p, int n, double x, double y, double z) {
         double dx = 0.0, dy = 0.0, dz = 0.0;
         if (WSUM) {
             if (!BOX && !MIXED) {
-                dx = d.x;
-                dy = d.y;
-                dz = d.z;
+                dx = x;
+                dy = y;
+                dz = z;
             } else if (FWD) {
-                dx = mimg<BOX>(R.px[j] - d.x, c.box, c.ib);
-                dy = mimg<BOX>(R.py[j] - d.y, c.box, c.ib);
-                dz = mimg<BOX>(R.pz[j] - d.z, c.box, c.ib);
+                dx = mimg<BOX>(R.px[j] - x, c.box, c.ib);
+                dy = mimg<BOX>(R.py[j] - y, c.box, c.ib);
+                dz = mimg<BOX>(R.pz[j] - z, c.box, c.ib);
             } else {
-                dx = mimg<BOX>(d.x - R.px[j], c.box, c.ib);
-                dy = mimg<BOX>(d.y - R.py[j], c.box, c.ib);
-                dz = mimg<BOX>(d.z - R.pz[j], c.box, c.ib);
+                dx = mimg<BOX>(x - R.px[j], c.box, c.ib);
+                dy = mimg<BOX>(y - R.py[j], c.box, c.ib);
+                dz = mimg<BOX>(z - R.pz[j], c.box, c.ib);
             }
         }
-        const int te = live ? add_sat(ze, d.n) : EMASK;
+        const int te = add_sat(ze, n);
         int kk = sub_sat(te, r.e);
-        if (kk > RENORM) kk = acc_shift<WSUM>(r, te);
-        acc_add<WSUM>(r, zm * d.p, kk, dx, dy, dz);
-        // the owner (lane is) is complete: broadcast its scaled sum
+        if (__builtin_amdgcn_ballot_w64(kk > RENORM) != 0) kk = acc_shift<WSUM>(r, te);
+        acc_add<WSUM>(r, zm * p, kk, dx, dy, dz);
         const double zz = r.A * ivd;
         zm = readlane_f64(__builtin_amdgcn_frexp_mant(zz), is);
         ze = __builtin_amdgcn_readlane(r.e + __builtin_amdgcn_frexp_exp(zz), is);
     };
-    DStep da = fetch(0), db;
-    for (int i = 0; i < nst; i += 2) {
-        db = fetch(i + 1);
-        step(i, da);
-        if (i + 1 < nst) {
-            da = fetch(i + 2);
-            step(i + 1, db);
+    bool done = false;
+    if constexpr (UNR) {
+        if (nst == BK) {
+            // full block: unrolled, so every LDS offset is an immediate and
+            // the serial chain carries no address arithmetic
+#pragma unroll
+            for (int i = 0; i < BK; ++i) {
+                const int is = FWD ? i : BK - 1 - i;
+                double x, y, z, uh;
+                step_point<FWD, !BOX && !MIXED>(S, is, x, y, z, uh);
+                step(is, KPl[tri_index<FWD>(is, 0)], KNl[is * BK], x, y, z);
+            }
+            done = true;
+        }
+    }
+    if (!done) {
+        // partial blocks (and the wider kernels, to bound code size): a
+        // step's values are read one step ahead so the LDS latency stays
+        // off the serial chain
+        struct DStep {
+            double p, x, y, z;
+            int n;
+        };
+        auto fetch = [&](int i) {
+            const int is = FWD ? min(i, nst - 1) : max(nst - 1 - i, 0);
+            DStep d;
+            d.p = KPl[tri_index<FWD>(is, 0)];
+            d.n = KNl[is * BK];
+            double uh;
+            step_point<FWD, !BOX && !MIXED>(S, is, d.x, d.y, d.z, uh);
+            return d;
+        };
+        DStep da = fetch(0), db;
+        for (int i = 0; i < nst; i += 2) {
+            db = fetch(i + 1);
+            step(FWD ? i : nst - 1 - i, da.p, da.n, da.x, da.y, da.z);
+            if (i + 1 < nst) {
+                da = fetch(i + 2);
+                step(FWD ? i + 1 : nst - 2 - i, db.p, db.n, db.x, db.y, db.z);
+            }
         }
     }
     if (q < N) {
@@ -656,8 +700,10 @@ __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bo
         const int ez = r.e + __builtin_amdgcn_frexp_exp(zz);
         const int sp = FWD ? q + 1 : q - 1; // step that reads this value
         if (sp >= 0 && sp < N) {
+            const double *su = stg_block(c.sm, sp / BK) + STG * (sp % BK);
             zm_block(c.sm, sp / BK)[sp % BK] = mz;
             ze_block(c.sm, sp / BK)[sp % BK] = ez;
+            zl_block(c.sm, sp / BK)[sp % BK] = log2_mant(mz) + step_const<FWD, !BOX && !MIXED>(su);
         }
         if (FWD) { // Z_f[q+1]
             zm_out[q + 1] = mz;
@@ -686,14 +732,18 @@ __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bo
 // Phase B of one wave.  Forward: live rows [LO, JJ) (blocks >= k);
 // backward: live rows [0, HI) (blocks <= k).  DG: this wave owns block k
 // (row LO forward, row HI-1 backward).
-template <bool FWD, int LO, int HI, bool DG, int JJ, bool BOX, bool MIXED, bool WSUM>
+template <bool FWD, int LO, int HI, bool DG, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR>
 __device__ __forceinline__ void wave_iter(Rows<JJ> &R, const RecCtx &c, int k, double *zm_out, double *ze_out,
                                           double *r_out) {
     const int prev = FWD ? k - 1 : k + 1;
     const bool has_prev = FWD ? k > 0 : k + 1 < c.nblk;
     if constexpr (DG) {
         constexpr int jd = FWD ? LO : HI - 1;
-        diagonal<FWD, jd, JJ, BOX, MIXED, WSUM>(R, c, k, has_prev, zm_out, ze_out, r_out);
+        // the serial chain is the critical path of phase B: its wave issues
+        // first whenever it is ready
+        __builtin_amdgcn_s_setprio(2);
+        diagonal<FWD, jd, JJ, BOX, MIXED, WSUM, UNR>(R, c, k, has_prev, zm_out, ze_out, r_out);
+        __builtin_amdgcn_s_setprio(0);
         if (has_prev) {
             if (FWD)
                 panel<FWD, LO + 1, HI, JJ, BOX, MIXED, WSUM>(R, c, prev);
@@ -706,7 +756,7 @@ __device__ __forceinline__ void wave_iter(Rows<JJ> &R, const RecCtx &c, int k, d
 }
 
 // Runtime (first live row / number of live rows, owner?) -> compiled variant.
-template <bool FWD, int X, int JJ, bool BOX, bool MIXED, bool WSUM>
+template <bool FWD, int X, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR>
 __device__ __forceinline__ void wave_dispatch(Rows<JJ> &R, const RecCtx &c, int k, int x, bool dg, double *zm_out,
                                               double *ze_out, double *r_out) {
     if constexpr (X <= JJ) {
@@ -714,25 +764,25 @@ __device__ __forceinline__ void wave_dispatch(Rows<JJ> &R, const RecCtx &c, int 
             if (FWD) {
                 if constexpr (X < JJ) {
                     if (dg)
-                        wave_iter<FWD, X, JJ, true, JJ, BOX, MIXED, WSUM>(R, c, k, zm_out, ze_out, r_out);
+                        wave_iter<FWD, X, JJ, true, JJ, BOX, MIXED, WSUM, UNR>(R, c, k, zm_out, ze_out, r_out);
                     else
-                        wave_iter<FWD, X, JJ, false, JJ, BOX, MIXED, WSUM>(R, c, k, zm_out, ze_out, r_out);
+                        wave_iter<FWD, X, JJ, false, JJ, BOX, MIXED, WSUM, UNR>(R, c, k, zm_out, ze_out, r_out);
                 }
             } else {
                 if constexpr (X > 0) {
                     if (dg)
-                        wave_iter<FWD, 0, X, true, JJ, BOX, MIXED, WSUM>(R, c, k, zm_out, ze_out, r_out);
+                        wave_iter<FWD, 0, X, true, JJ, BOX, MIXED, WSUM, UNR>(R, c, k, zm_out, ze_out, r_out);
                     else
-                        wave_iter<FWD, 0, X, false, JJ, BOX, MIXED, WSUM>(R, c, k, zm_out, ze_out, r_out);
+                        wave_iter<FWD, 0, X, false, JJ, BOX, MIXED, WSUM, UNR>(R, c, k, zm_out, ze_out, r_out);
                 }
             }
         } else {
-            wave_dispatch<FWD, X + 1, JJ, BOX, MIXED, WSUM>(R, c, k, x, dg, zm_out, ze_out, r_out);
+            wave_dispatch<FWD, X + 1, JJ, BOX, MIXED, WSUM, UNR>(R, c, k, x, dg, zm_out, ze_out, r_out);
         }
     }
 }
 
-template <bool FWD, int JJ, bool BOX, bool MIXED, bool WSUM>
+template <bool FWD, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR>
 __device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c) {
     const int t = c.t, T = c.T, N = c.N, W = c.W, w = t >> 6, nblk = c.nblk;
     const size_t NN = c.NN;
@@ -778,12 +828,20 @@ __device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDes
     // first block staged, first broadcast value: Z_f[0] = 1 (V^[1,0] = 0),
     // or Z_b[N+1] / N = 1 / N
     const int b0 = FWD ? 0 : nblk - 1;
-    if (w == 0) stage_store(c, b0, stage_load<BOX, MIXED>(c, b0, range_bad));
+    const int s0 = FWD ? 0 : N - 1;
+    if (w == 0) {
+        const Stage g = stage_load<BOX, MIXED>(c, b0, range_bad);
+        stage_store(c, b0, g);
+        if ((t & 63) == s0 % BK) {
+            const double z0 = FWD ? 1.0 : 1.0 / (double)N;
+            const double m0 = __builtin_amdgcn_frexp_mant(z0);
+            constexpr bool DOT = !BOX && !MIXED;
+            zm_block(c.sm, b0)[s0 % BK] = m0;
+            ze_block(c.sm, b0)[s0 % BK] = __builtin_amdgcn_frexp_exp(z0);
+            zl_block(c.sm, b0)[s0 % BK] = log2_mant(m0) + (DOT ? (FWD ? g.Df : g.Db) : (FWD ? 0.0 : g.h));
+        }
+    }
     if (t == 0) {
-        const int s0 = FWD ? 0 : N - 1;
-        const double z0 = FWD ? 1.0 : 1.0 / (double)N;
-        zm_block(c.sm, s0 / BK)[s0 % BK] = __builtin_amdgcn_frexp_mant(z0);
-        ze_block(c.sm, s0 / BK)[s0 % BK] = __builtin_amdgcn_frexp_exp(z0);
         if (FWD) {
             zm_out[0] = 1.0;
             ze_out[0] = 0.0;
@@ -792,6 +850,9 @@ __device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDes
             ze_out[N + 1] = 0.0;
         }
     }
+    // the diagonal triangle's fills (see the LDS map)
+    for (int i = t; i < BK * BK; i += T) kn_base(c.sm)[i] = EMASK;
+    for (int i = t; i < KTRI; i += T) c.sm[L_KP + i] = 0.0;
     // loads of the rows are complete before the loop (a wait inside it would
     // also wait for the staging loads issued there)
     __builtin_amdgcn_s_waitcnt(0);
@@ -808,7 +869,11 @@ __device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDes
         Stage g{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (stage) g = stage_load<BOX, MIXED>(c, nb, range_bad);
         diag_terms<FWD, BOX, MIXED>(c, k);
-        if (has_prev) diag_partial<FWD, BOX, MIXED, WSUM>(c, k, prev);
+        if (has_prev) { // the longest work of phase A
+            __builtin_amdgcn_s_setprio(1);
+            diag_partial<FWD, BOX, MIXED, WSUM>(c, k, prev);
+            __builtin_amdgcn_s_setprio(0);
+        }
         if (stage) stage_store(c, nb, g);
         __syncthreads();
         // phase B
@@ -821,7 +886,7 @@ __device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDes
             x = k < w ? 0 : min((k - w) / W + 1, JJ);
             dg = x > 0 && (x - 1) * W + w == k;
         }
-        wave_dispatch<FWD, 0, JJ, BOX, MIXED, WSUM>(R, c, k, x, dg, zm_out, ze_out, r_out);
+        wave_dispatch<FWD, 0, JJ, BOX, MIXED, WSUM, UNR>(R, c, k, x, dg, zm_out, ze_out, r_out);
         __syncthreads();
     }
     if (range_bad) set_flag(a.flags, ST_RANGE);
@@ -833,7 +898,7 @@ template <int JJ, int J, bool FWD, bool BOX, bool MIXED, bool WSUM>
 __device__ __forceinline__ void rec_dispatch(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c, int jj) {
     if constexpr (JJ <= J) {
         if (jj == JJ)
-            recursion_rows<FWD, JJ, BOX, MIXED, WSUM>(a, sd, c);
+            recursion_rows<FWD, JJ, BOX, MIXED, WSUM, (J <= 2)>(a, sd, c);
         else
             rec_dispatch<JJ + 1, J, FWD, BOX, MIXED, WSUM>(a, sd, c, jj);
     }
