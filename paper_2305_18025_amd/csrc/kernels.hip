@@ -161,11 +161,17 @@ __device__ __forceinline__ void set_flag(int32_t *flags, int bits) {
 //
 // Exponent bookkeeping: an accumulator (A, e) stands for A 2^e; a term
 // t 2^te is added as A += t 2^(te - e) while te - e <= RENORM, so A stays
-// below 2^(RENORM + 13) and terms more than 2^1074 below A underflow
-// harmlessly.  A larger term (rare: a much closer pair than any before)
-// first moves the reference: A, W scaled by 2^(e - te), e = te.
+// below 2^(RENORM + 13).  A larger term first moves the reference to
+// e = te + RMARGIN (A, W scaled to match), leaving room for later terms up
+// to 2^(RENORM + RMARGIN) above it; A stays a normal number (at least
+// 2^-RMARGIN times a term), and terms more than 2^114 below the largest
+// underflow harmlessly.  In the gauge used here the terms of a row grow
+// along the recursion (Z_f gains a link-spring factor per step), so the
+// panels take the steps of each block in reverse order, largest first: the
+// reference then moves about once per block instead of every few steps.
 constexpr int BK = 64;
 constexpr int RENORM = 960;
+constexpr int RMARGIN = 960;
 constexpr int KSPLIT = 8;   // most waves that share the previous block's terms for the diagonal rows
                             // (8 in 16-wave workgroups, else 4)
 constexpr int KTRI = BK * (BK + 1) / 2;
@@ -230,20 +236,21 @@ struct Acc {
     int e;
 };
 
-// Move the reference of (A, W) to te if the term t 2^te is more than
-// 2^RENORM above it; returns te - e for the (possibly new) reference.
+// Move the reference of (A, W) to te + RMARGIN if the term t 2^te is more
+// than 2^RENORM above it; returns te - e for the (possibly new) reference.
 template <bool WSUM>
 __device__ __forceinline__ int acc_shift(Acc &r, int te) {
     int k = sub_sat(te, r.e);
     if (k > RENORM) {
-        r.A = ldexp(r.A, -k);
+        const int sh = add_sat(k, RMARGIN);
+        r.A = ldexp(r.A, -sh);
         if (WSUM) {
-            r.Wx = ldexp(r.Wx, -k);
-            r.Wy = ldexp(r.Wy, -k);
-            r.Wz = ldexp(r.Wz, -k);
+            r.Wx = ldexp(r.Wx, -sh);
+            r.Wy = ldexp(r.Wy, -sh);
+            r.Wz = ldexp(r.Wz, -sh);
         }
-        r.e = te;
-        k = 0;
+        r.e = add_sat(te, RMARGIN);
+        k = -RMARGIN;
     }
     return k;
 }
@@ -494,7 +501,9 @@ __device__ __forceinline__ void panel(Rows<JJ> &R, const RecCtx &c, int blk) {
         const double *S = stg_block(c.sm, blk);
         const double *Z = zl_block(c.sm, blk);
         const int *E = ze_block(c.sm, blk);
-        auto at = [&](int n) { return FWD ? n : nst - 1 - n; }; // -1 .. BK: guard entries at the ends
+        // the block's steps from the last of the recursion's order to the
+        // first (largest terms first); -1 .. BK: guard entries at the ends
+        auto at = [&](int n) { return FWD ? nst - 1 - n : n; };
         double ax, ay, az, ah, bx, by, bz, bh, za, zb;
         int ea, eb;
         int i = at(0);
@@ -585,7 +594,7 @@ __device__ __forceinline__ void diag_partial(const RecCtx &c, int k, int prev) {
     const double *Z = zl_block(c.sm, prev);
     const int *E = ze_block(c.sm, prev);
     for (int n = i0; n < i1; ++n) {
-        const int i = FWD ? n : nst - 1 - n;
+        const int i = FWD ? nst - 1 - n : n; // largest terms first, as in the panels
         double ux, uy, uz, uh;
         step_point<FWD, !BOX && !MIXED>(S, i, ux, uy, uz, uh);
         panel_step<FWD, 0, 1, 1, BOX, MIXED, WSUM>(R, c, Z[i], E[i], ux, uy, uz);
