@@ -481,7 +481,9 @@ __device__ __forceinline__ void panel_step(Rows<JJ> &R, const RecCtx &c, double 
             k[g] = sub_sat(add_sat(ze, (int)r[g]), R.a[LO + g].e);
             big |= k[g] > RENORM;
         }
-        if (big) {
+        // wave-uniform and rare (steps go largest first): a real branch, so
+        // the common path carries none of the rescaling instructions
+        if (__builtin_expect(__builtin_amdgcn_ballot_w64(big) != 0, 0)) {
 #pragma unroll
             for (int g = 0; g < G; ++g) k[g] = acc_shift<WSUM>(R.a[LO + g], add_sat(ze, (int)r[g]));
         }
@@ -490,10 +492,11 @@ __device__ __forceinline__ void panel_step(Rows<JJ> &R, const RecCtx &c, double 
     }
 }
 
-// Panel: rows [LO, HI) add the terms of the steps of block blk.  Steps go
-// in pairs with two alternating sets of step values, each read one step
+// Panel: rows [LO, HI) add the terms of the steps of block blk.  Full
+// blocks in the 1- and 2-row kernels run an unrolled loop; otherwise steps
+// go in pairs with two alternating sets of step values, each read one step
 // ahead, so no values are copied between iterations.
-template <bool FWD, int LO, int HI, int JJ, bool BOX, bool MIXED, bool WSUM>
+template <bool FWD, int LO, int HI, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR>
 __device__ __forceinline__ void panel(Rows<JJ> &R, const RecCtx &c, int blk) {
     if constexpr (HI > LO) {
         constexpr bool DOT = !BOX && !MIXED;
@@ -504,6 +507,20 @@ __device__ __forceinline__ void panel(Rows<JJ> &R, const RecCtx &c, int blk) {
         // the block's steps from the last of the recursion's order to the
         // first (largest terms first); -1 .. BK: guard entries at the ends
         auto at = [&](int n) { return FWD ? nst - 1 - n : n; };
+        if constexpr (UNR) {
+            if (nst == BK) {
+                // full block (1- and 2-row kernels): no tail test, four steps
+                // per loop trip with immediate LDS offsets
+#pragma unroll 4
+                for (int n = 0; n < BK; ++n) {
+                    const int ii = FWD ? BK - 1 - n : n;
+                    double ux, uy, uz, uh;
+                    step_point<FWD, DOT>(S, ii, ux, uy, uz, uh);
+                    panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM>(R, c, Z[ii], E[ii], ux, uy, uz);
+                }
+                return;
+            }
+        }
         double ax, ay, az, ah, bx, by, bz, bh, za, zb;
         int ea, eb;
         int i = at(0);
@@ -755,12 +772,12 @@ __device__ __forceinline__ void wave_iter(Rows<JJ> &R, const RecCtx &c, int k, d
         __builtin_amdgcn_s_setprio(0);
         if (has_prev) {
             if (FWD)
-                panel<FWD, LO + 1, HI, JJ, BOX, MIXED, WSUM>(R, c, prev);
+                panel<FWD, LO + 1, HI, JJ, BOX, MIXED, WSUM, UNR>(R, c, prev);
             else
-                panel<FWD, LO, HI - 1, JJ, BOX, MIXED, WSUM>(R, c, prev);
+                panel<FWD, LO, HI - 1, JJ, BOX, MIXED, WSUM, UNR>(R, c, prev);
         }
     } else {
-        if (has_prev) panel<FWD, LO, HI, JJ, BOX, MIXED, WSUM>(R, c, prev);
+        if (has_prev) panel<FWD, LO, HI, JJ, BOX, MIXED, WSUM, UNR>(R, c, prev);
     }
 }
 
