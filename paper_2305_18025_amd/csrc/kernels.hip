@@ -672,7 +672,7 @@ __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bo
         }
         const int te = add_sat(ze, n);
         int kk = sub_sat(te, r.e);
-        if (__builtin_amdgcn_ballot_w64(kk > RENORM) != 0) kk = acc_shift<WSUM>(r, te);
+        if (__builtin_expect(__builtin_amdgcn_ballot_w64(kk > RENORM) != 0, 0)) kk = acc_shift<WSUM>(r, te);
         acc_add<WSUM>(r, zm * p, kk, dx, dy, dz);
         const double zz = r.A * ivd;
         zm = readlane_f64(__builtin_amdgcn_frexp_mant(zz), is);
@@ -682,13 +682,27 @@ __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bo
     if constexpr (UNR) {
         if (nst == BK) {
             // full block: unrolled, so every LDS offset is an immediate and
-            // the serial chain carries no address arithmetic
+            // the serial chain carries no address arithmetic; each step's
+            // values are read before the previous step's chain runs
+            double xs[2], ys[2], zs[2], ps[2], uh;
+            int ns2[2];
+            {
+                const int is = FWD ? 0 : BK - 1;
+                step_point<FWD, !BOX && !MIXED>(S, is, xs[0], ys[0], zs[0], uh);
+                ps[0] = KPl[tri_index<FWD>(is, 0)];
+                ns2[0] = KNl[is * BK];
+            }
 #pragma unroll
             for (int i = 0; i < BK; ++i) {
                 const int is = FWD ? i : BK - 1 - i;
-                double x, y, z, uh;
-                step_point<FWD, !BOX && !MIXED>(S, is, x, y, z, uh);
-                step(is, KPl[tri_index<FWD>(is, 0)], KNl[is * BK], x, y, z);
+                const int cu = i & 1, nx = cu ^ 1;
+                if (i + 1 < BK) {
+                    const int is2 = FWD ? i + 1 : BK - 2 - i;
+                    step_point<FWD, !BOX && !MIXED>(S, is2, xs[nx], ys[nx], zs[nx], uh);
+                    ps[nx] = KPl[tri_index<FWD>(is2, 0)];
+                    ns2[nx] = KNl[is2 * BK];
+                }
+                step(is, ps[cu], ns2[cu], xs[cu], ys[cu], zs[cu]);
             }
             done = true;
         }
