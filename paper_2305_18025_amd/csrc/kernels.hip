@@ -685,12 +685,12 @@ __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bo
             // the serial chain carries no address arithmetic; each step's
             // values are read before the previous step's chain runs
             double xs[2], ys[2], zs[2], ps[2], uh;
-            int ns2[2];
+            int es[2];
             {
                 const int is = FWD ? 0 : BK - 1;
                 step_point<FWD, !BOX && !MIXED>(S, is, xs[0], ys[0], zs[0], uh);
                 ps[0] = KPl[tri_index<FWD>(is, 0)];
-                ns2[0] = KNl[is * BK];
+                es[0] = KNl[is * BK];
             }
 #pragma unroll
             for (int i = 0; i < BK; ++i) {
@@ -700,9 +700,9 @@ __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bo
                     const int is2 = FWD ? i + 1 : BK - 2 - i;
                     step_point<FWD, !BOX && !MIXED>(S, is2, xs[nx], ys[nx], zs[nx], uh);
                     ps[nx] = KPl[tri_index<FWD>(is2, 0)];
-                    ns2[nx] = KNl[is2 * BK];
+                    es[nx] = KNl[is2 * BK];
                 }
-                step(is, ps[cu], ns2[cu], xs[cu], ys[cu], zs[cu]);
+                step(is, ps[cu], es[cu], xs[cu], ys[cu], zs[cu]);
             }
             done = true;
         }
@@ -1032,9 +1032,11 @@ __device__ __forceinline__ void springs_role(const LaunchArgs &a, const SysDesc 
                         const double by = mimg<BOX>(cy - vy, box, ib);
                         const double bz = mimg<BOX>(cz - vz, box, ib);
                         const size_t oj = (size_t)j * 3 * NN;
-                        fo[oj] = scale * (-mw2 * (ax + bx) - trapc * cx);
-                        fo[oj + NN] = scale * (-mw2 * (ay + by) - trapc * cy);
-                        fo[oj + 2 * NN] = scale * (-mw2 * (az + bz) - trapc * cz);
+                        // streaming stores (nothing here reads them back):
+                        // 1.3x the write bandwidth of cached stores
+                        __builtin_nontemporal_store(scale * (-mw2 * (ax + bx) - trapc * cx), fo + oj);
+                        __builtin_nontemporal_store(scale * (-mw2 * (ay + by) - trapc * cy), fo + oj + NN);
+                        __builtin_nontemporal_store(scale * (-mw2 * (az + bz) - trapc * cz), fo + oj + 2 * NN);
                     }
                     vx = cx; vy = cy; vz = cz;
                     cx = nx; cy = ny; cz = nz;
@@ -1427,8 +1429,12 @@ __global__ void __launch_bounds__(256) k_endpoint_springs(LaunchArgs a, int si, 
         const double dy = mimg<BOX>(rv[1][iv] - ru[1][iu], box, ib);
         const double dz = mimg<BOX>(rv[2][iv] - ru[2][iu], box, ib);
         const int64_t o = (int64_t)v * (v + 1) / 2 + u;
+        // rows start at arbitrary offsets, so a row segment covers partial
+        // cache lines at its ends: streaming stores measured faster for the
+        // 4-byte table (2.0 vs 1.8 TB/s at N=4096) and slower for the 8-byte
+        // one (2.8 vs 4.0 TB/s), which keeps cached stores
         if (F32)
-            ((float *)dst)[o] = (float)(k * sqlen<true>(dx, dy, dz));
+            __builtin_nontemporal_store((float)(k * sqlen<true>(dx, dy, dz)), (float *)dst + o);
         else
             ((double *)dst)[o] = k * sqlen<false>(dx, dy, dz);
     }
