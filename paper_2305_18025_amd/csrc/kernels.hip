@@ -1194,10 +1194,12 @@ __global__ void __launch_bounds__(512) k_exchange_wide(LaunchArgs a) {
     exchange_body<J, BOX, MIXED>(a);
 }
 
-// One workgroup per system.
+// One workgroup per system (memory-latency bound: 512 threads keep twice the
+// loads of 256 in flight; at 1024 the 128-register limit makes it spill).
+constexpr int FIN_T = 512;
 template <bool BOX>
-__global__ void __launch_bounds__(256) k_finalize(LaunchArgs a) {
-    __shared__ double red[256];
+__global__ void __launch_bounds__(FIN_T) k_finalize(LaunchArgs a) {
+    __shared__ double red[FIN_T];
     const int si = blockIdx.x;
     finalize<BOX>(a, a.sys[si], si, red);
 }
@@ -1205,9 +1207,9 @@ __global__ void __launch_bounds__(256) k_finalize(LaunchArgs a) {
 hipError_t launch_finalize(const LaunchArgs &a, int S, hipStream_t st) {
     if (S <= 0) return hipSuccess;
     if (a.box > 0)
-        hipLaunchKernelGGL(k_finalize<true>, dim3(S), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_finalize<true>, dim3(S), dim3(FIN_T), 0, st, a);
     else
-        hipLaunchKernelGGL(k_finalize<false>, dim3(S), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_finalize<false>, dim3(S), dim3(FIN_T), 0, st, a);
     return hipGetLastError();
 }
 
