@@ -32,9 +32,9 @@
 //    Z_f[u-1] is known, every accumulator v >= u adds Z_f[u-1] K(u,v), and
 //    the owner of v = u then holds Z_f[u] = acc/u.  Steps go in blocks of 64:
 //    the wave owning a block's 64 accumulators runs its 64 steps serially
-//    with lane broadcasts, then all waves add the block's 64 terms to every
-//    later accumulator without synchronisation; one workgroup barrier per
-//    block.  The backward recursion is the same with rows and columns
+//    with lane broadcasts, while the other waves add the previous block's
+//    64 terms to every later accumulator without synchronisation; two
+//    workgroup barriers per block.  The backward recursion is the same with rows and columns
 //    exchanged; forward and backward run concurrently in separate
 //    workgroups.
 // 4. Forces without materialised probabilities.  Pr[v -> u] (u <= v) is the
@@ -136,8 +136,9 @@ __device__ __forceinline__ void set_flag(int32_t *flags, int bits) {
 // Forward, iteration k (block k = steps and accumulators [64 k, 64 k + 64)):
 //   phase A (all waves): the exponentials of block k's own triangle
 //     K(s+1, q+1), s <= q, go to LDS; block k-1's terms for block k's 64
-//     accumulators are summed in slices by up to 4 waves (partial sums to
-//     LDS);
+//     accumulators are summed in slices by 4 waves (8 in 16-wave
+//     workgroups; partial sums to LDS) while the last wave stages block
+//     k+1's endpoints;
 //   barrier;
 //   phase B: the wave owning block k merges the partial sums and runs the
 //     block's 64 steps serially: at step s each lane q >= s adds
