@@ -1,0 +1,160 @@
+"""Error behaviour of the C ABI on a real device.
+
+Every rejected call here is refused by the host-side checks of the library
+before anything is launched (argument ranges, missing system or workspace,
+misaligned or too small workspace, null or aliased pointers, unknown modes);
+each is checked for the return code the header documents, and the handle is
+then checked to still evaluate correctly, against the oracle's exact
+brute-force sum over permutations.
+"""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import brute
+from paper_2305_18025_amd import _lib, inputs
+
+pytestmark = pytest.mark.gpu
+
+OK, EINVAL, ENOSYS, EWORKSPACE, ERANGE = (_lib.PIMDB_OK, _lib.PIMDB_EINVAL, _lib.PIMDB_ENOSYS,
+                                          _lib.PIMDB_EWORKSPACE, _lib.PIMDB_ERANGE)
+
+
+@pytest.fixture()
+def api():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.pimdb_create(ctypes.byref(h), 0) == OK
+    yield lib, h
+    torch.cuda.synchronize()
+    assert lib.pimdb_destroy(h) == OK
+
+
+def _arr(ctype, vals):
+    return (ctype * len(vals))(*vals)
+
+
+def _set_batch(lib, h, N, P, beta, m, w):
+    S = len(N)
+    return lib.pimdb_set_batch(h, S, _arr(ctypes.c_int64, N), _arr(ctypes.c_int32, P),
+                               _arr(ctypes.c_double, beta), _arr(ctypes.c_double, m), _arr(ctypes.c_double, w))
+
+
+def test_create_rejects_bad_device():
+    lib = _lib.load()
+    h = ctypes.c_void_p(1)
+    assert lib.pimdb_create(ctypes.byref(h), torch.cuda.device_count()) == EINVAL
+    assert not h.value
+    assert lib.pimdb_create(ctypes.byref(h), -1) == EINVAL
+    assert lib.pimdb_create(None, 0) == EINVAL
+
+
+def test_calls_before_a_system_is_set(api):
+    lib, h = api
+    buf = torch.zeros(64, dtype=torch.float64, device="cuda")
+    assert lib.pimdb_exchange_energy(h, buf.data_ptr(), buf.data_ptr()) == ENOSYS
+    assert lib.pimdb_exchange_forces(h, buf.data_ptr(), buf[32:].data_ptr(), None) == ENOSYS
+    assert lib.pimdb_endpoint_springs(h, buf.data_ptr(), 0, 0, buf.data_ptr()) == ENOSYS
+    assert lib.pimdb_total_elements(h) == 0
+    assert lib.pimdb_system_offset(h, 0) == -1
+    assert b"no system" in lib.pimdb_last_error(h)
+
+
+@pytest.mark.parametrize("N,P,beta,m,w,code", [
+    (0, 4, 1.0, 1.0, 1.0, EINVAL),                      # N < 1
+    (-3, 4, 1.0, 1.0, 1.0, EINVAL),
+    (8, 1, 1.0, 1.0, 1.0, EINVAL),                      # P < 2
+    (8, 4, 0.0, 1.0, 1.0, EINVAL),                      # beta not positive
+    (8, 4, -1.0, 1.0, 1.0, EINVAL),
+    (8, 4, math.nan, 1.0, 1.0, EINVAL),
+    (8, 4, math.inf, 1.0, 1.0, EINVAL),
+    (8, 4, 1.0, 0.0, 1.0, EINVAL),                      # mass
+    (8, 4, 1.0, 1.0, math.nan, EINVAL),                 # omega_P
+    (_lib.MAX_N + 1, 4, 1.0, 1.0, 1.0, ERANGE),         # above the register-resident limit
+])
+def test_set_system_rejects(api, N, P, beta, m, w, code):
+    lib, h = api
+    assert lib.pimdb_set_system(h, N, P, beta, m, w) == code
+    assert lib.pimdb_total_elements(h) == 0             # nothing was set
+
+
+def test_set_batch_rejects(api):
+    lib, h = api
+    assert lib.pimdb_set_batch(h, 0, None, None, None, None, None) == EINVAL
+    # the batch-size limit is checked before any array element is read
+    one = [1.0]
+    assert lib.pimdb_set_batch(h, 65537, _arr(ctypes.c_int64, [8]), _arr(ctypes.c_int32, [4]),
+                               _arr(ctypes.c_double, one), _arr(ctypes.c_double, one),
+                               _arr(ctypes.c_double, one)) == ERANGE
+    # one bad system rejects the whole batch
+    assert _set_batch(lib, h, [8, 16, 0], [4, 4, 4], [1.0] * 3, [1.0] * 3, [1.0] * 3) == EINVAL
+    assert _set_batch(lib, h, [8, 4097], [4, 4], [1.0] * 2, [1.0] * 2, [1.0] * 2) == ERANGE
+    assert lib.pimdb_total_elements(h) == 0
+
+
+def test_setters_and_tuning_reject(api):
+    lib, h = api
+    for L in (-1.0, math.nan, math.inf):
+        assert lib.pimdb_set_box(h, L) == EINVAL
+    for wt in (-0.5, math.nan):
+        assert lib.pimdb_set_trap(h, wt) == EINVAL
+    assert lib.pimdb_set_precision(h, 2) == EINVAL
+    for threads, per in [(96, 1), (2048, 1), (64, 3), (64, 0), (1024, 4), (1024, 8)]:
+        assert lib.pimdb_set_tuning(h, threads, per) == EINVAL, (threads, per)
+    assert lib.pimdb_set_system(h, 1024, 4, 1.0, 1.0, 1.0) == OK
+    assert lib.pimdb_set_tuning(h, 256, 2) == EINVAL     # 512 rows < N = 1024
+    assert lib.pimdb_set_tuning(h, 512, 2) == OK
+    # a batch that the override cannot hold is refused and the old one kept
+    assert lib.pimdb_set_system(h, 2048, 4, 1.0, 1.0, 1.0) == EINVAL
+    assert lib.pimdb_total_elements(h) == 3 * 4 * 1024
+    t, p = ctypes.c_int(), ctypes.c_int()
+    assert lib.pimdb_get_tuning(h, ctypes.byref(t), ctypes.byref(p)) == OK
+    assert (t.value, p.value) == (512, 2)
+
+
+def test_workspace_and_pointer_errors_then_correct_result(api):
+    lib, h = api
+    s = inputs.config_tiny()
+    assert lib.pimdb_set_system(h, s.N, s.P, s.beta, s.m, s.omegaP) == OK
+    n = int(lib.pimdb_total_elements(h))
+    assert n == 3 * s.P * s.N
+    pos = torch.from_numpy(inputs.to_soa(s.R).reshape(-1)).to("cuda")
+    F = torch.zeros(n, dtype=torch.float64, device="cuda")
+    E = torch.zeros(1, dtype=torch.float64, device="cuda")
+    # no workspace bound
+    assert lib.pimdb_exchange_forces(h, pos.data_ptr(), F.data_ptr(), E.data_ptr()) == EWORKSPACE
+    need = int(lib.pimdb_workspace_bytes(h))
+    assert need > 0
+    ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    base = ws.data_ptr()
+    assert base % 256 == 0
+    assert lib.pimdb_bind_workspace(h, None, need) == EINVAL
+    assert lib.pimdb_bind_workspace(h, base + 8, need) == EINVAL          # misaligned
+    assert lib.pimdb_bind_workspace(h, base, need - 8) == EWORKSPACE      # too small
+    assert lib.pimdb_exchange_forces(h, pos.data_ptr(), F.data_ptr(), E.data_ptr()) == EWORKSPACE
+    assert lib.pimdb_bind_workspace(h, base, need) == OK
+    # pointer errors
+    assert lib.pimdb_exchange_forces(h, None, F.data_ptr(), E.data_ptr()) == EINVAL
+    assert lib.pimdb_exchange_forces(h, pos.data_ptr(), None, E.data_ptr()) == EINVAL
+    assert lib.pimdb_exchange_forces(h, pos.data_ptr(), pos.data_ptr(), E.data_ptr()) == EINVAL
+    assert lib.pimdb_debug_get(h, pos.data_ptr(), 1, _lib.DEBUG_FORWARD, F.data_ptr()) == EINVAL
+    assert lib.pimdb_debug_get(h, pos.data_ptr(), 0, 0, F.data_ptr()) == EINVAL
+    assert lib.pimdb_debug_get(h, pos.data_ptr(), 0, 5, F.data_ptr()) == EINVAL
+    assert lib.pimdb_endpoint_springs(h, pos.data_ptr(), -1, 0, F.data_ptr()) == EINVAL
+    vel = torch.zeros_like(pos)
+    assert lib.pimdb_md_step(h, pos.data_ptr(), vel.data_ptr(), F.data_ptr(), E.data_ptr(), math.nan) == EINVAL
+    assert b"dt" in lib.pimdb_last_error(h)
+    torch.cuda.synchronize()
+    assert float(vel.abs().max()) == 0.0                  # the refused step touched nothing
+    # the handle still evaluates correctly
+    assert lib.pimdb_exchange_forces(h, pos.data_ptr(), F.data_ptr(), E.data_ptr()) == OK
+    torch.cuda.synchronize()
+    flags = ctypes.c_int32(-1)
+    assert lib.pimdb_status(h, ctypes.byref(flags)) == OK and flags.value == 0
+    b = brute.exchange(s.R, s.beta, s.m, s.omegaP)
+    Fg = inputs.from_soa(F.cpu().numpy().reshape(s.P, 3, s.N))
+    assert abs(float(E[0]) - b["V"]) <= 1e-10 * abs(b["V"])
+    assert np.abs(Fg - b["F"]).max() <= 1e-10 * np.abs(b["F"]).max()
