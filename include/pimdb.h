@@ -81,7 +81,11 @@ extern "C" {
 /* ---- device status bits (pimdb_status) ---- */
 #define PIMDB_STATUS_NONFINITE_INPUT 1  /* a position was NaN or infinite */
 #define PIMDB_STATUS_NONFINITE_OUTPUT 2 /* an energy or force came out NaN or infinite */
-#define PIMDB_STATUS_RANGE 4            /* a spring exponent beta*k*|d|^2 exceeded 2^29 in log2 units */
+#define PIMDB_STATUS_RANGE 4            /* out of range, results invalid: a spring exponent
+                                           beta*k*|d|^2*log2(e) above 2^28, or a recursion value
+                                           whose binary exponent passed +-2^29 (the chain's
+                                           cumulative spring exponents, e.g. particles with
+                                           consecutive labels thousands of length units apart) */
 
 /* ---- what pimdb_debug_get exports ---- */
 #define PIMDB_DEBUG_PROBABILITIES 1 /* dense N x N per system, [l-1][l'-1] = Pr[l -> l'] */

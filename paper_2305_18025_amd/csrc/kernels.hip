@@ -60,6 +60,7 @@ constexpr double LOG2E = 1.4426950408889634;
 constexpr double XLO = -536870912.0;     // -2^29: lower clamp of an exported term exponent
 constexpr double XHI = 268435456.0;      //  2^28: bound on h = -kappa |d_ref|^2
 constexpr int EMIN = -(1 << 30);         // exponent of an empty accumulator
+constexpr int EZ_LIM = 1 << 29;          // bound on the exponent of a published Z value
 constexpr int EMASK = -(3 << 29);        // term exponent that adds nothing (below EMIN)
 
 enum StatusBits { ST_NONFINITE_IN = 1, ST_NONFINITE_OUT = 2, ST_RANGE = 4 };
@@ -339,6 +340,7 @@ struct RecCtx {
     int N, T, t, W, nblk;
     double kap, box, ib;
     double ox, oy, oz; // origin of the dot form (bead 1 of particle 0)
+    int32_t *flags;    // status word
 };
 
 // Staged data of one particle.
@@ -739,6 +741,10 @@ __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bo
         const double zz = r.A * ivd;
         const double mz = __builtin_amdgcn_frexp_mant(zz);
         const int ez = r.e + __builtin_amdgcn_frexp_exp(zz);
+        // the open-chain gauge carries the chain's cumulative spring
+        // exponents; beyond 2^29 binary orders they would approach the
+        // empty-accumulator sentinel, so the input is out of range
+        if (__builtin_expect(ez > EZ_LIM || ez < -EZ_LIM, 0)) set_flag(c.flags, ST_RANGE);
         const int sp = FWD ? q + 1 : q - 1; // step that reads this value
         if (sp >= 0 && sp < N) {
             const double *su = stg_block(c.sm, sp / BK) + STG * (sp % BK);
@@ -963,6 +969,7 @@ __device__ __forceinline__ void recursion_role(const LaunchArgs &a, const SysDes
     c.ox = c.b1[0];
     c.oy = c.b1[c.NN];
     c.oz = c.b1[2 * c.NN];
+    c.flags = a.flags;
     const int jj = (sd.N + c.T - 1) / c.T;
     rec_dispatch<1, J, FWD, BOX, MIXED, WSUM>(a, sd, c, jj);
 }

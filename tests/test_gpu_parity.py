@@ -234,6 +234,74 @@ def test_chain_configuration_renormalisation(scale):
     _assert_parity(eng, F, E, [s], TOL64)
 
 
+def _paired(npairs, P, c, D, seed):
+    """Linked pairs (particle 2i's beads run from A_i to B_i, 2i+1's back from
+    B_i to A_i, segment length c), pairs D apart along x."""
+    rng = np.random.default_rng(seed)
+    R = np.zeros((2 * npairs, P, 3))
+    f = np.linspace(0.0, 1.0, P)[:, None]
+    for i in range(npairs):
+        A = np.array([D * i, 0.0, 0.0])
+        B = A + np.array([0.0, c, 0.0])
+        R[2 * i] = A + (B - A) * f
+        R[2 * i + 1] = B + (A - B) * f
+    return R + rng.normal(0.0, 0.05, R.shape)
+
+
+def test_linked_pairs():
+    """Exchange-dominated input on which the paper's simple two-term shift
+    overflows double precision (the pair cycle lies ~2 k c^2 = 3200 below
+    both of its candidates; the CPU ablation test shows the NaN): 150 linked
+    pairs, c = 20, P = 8, several blocks and a ragged tail."""
+    s = System(_paired(150, 8, 20.0, 4.0, seed=2), beta=1.0)
+    eng, pos = _engine([s])
+    F, E = eng.forces(pos)
+    assert eng.status() == 0
+    _assert_parity(eng, F, E, [s], TOL64)
+
+
+def _clustered(ncl, per, spread, P, seed):
+    """ncl clusters of per particles with consecutive labels: centres uniform
+    in [0, spread)^3, members N(0, 0.7^2) about their centre, beads
+    N(0, 0.3^2) about their particle."""
+    rng = np.random.default_rng(seed)
+    cen = rng.uniform(0.0, spread, (ncl, 3))
+    c = np.repeat(cen, per, axis=0) + rng.normal(0.0, 0.7, (ncl * per, 3))
+    return c[:, None, :] + rng.normal(0.0, 0.3, (ncl * per, P, 3))
+
+
+@pytest.mark.parametrize("threads,per", [(512, 1), (256, 2)])
+def test_wide_clustered_system(threads, per):
+    """64 clusters of 8 spread over a cube of side 400: exchange inside the
+    clusters, points up to ~470 units from the dot form's origin, where its
+    expanded exponent rounds most (kappa |p - o|^2 ~ 2.5e6 binary orders)."""
+    s = System(_clustered(64, 8, 400.0, 16, seed=3), beta=1.0)
+    eng, pos = _engine([s], threads=threads, per_thread=per)
+    F, E = eng.forces(pos)
+    assert eng.status() == 0
+    _assert_parity(eng, F, E, [s], TOL64)
+
+
+def test_cumulative_exponent_range_flag():
+    """The same clusters over a cube of side 3000: each spring between
+    consecutive labels in different clusters stays below the per-spring bound
+    (~1.5e8 < 2^28 binary orders) but they add up to ~2.7e9 along the chain,
+    past the recursions' integer exponents.  Energy-only and force calls
+    must both raise PIMDB_STATUS_RANGE rather than return unflagged numbers;
+    a compact system on the same engine afterwards is clean again."""
+    wide = System(_clustered(64, 8, 3000.0, 16, seed=3), beta=1.0)
+    eng, pos = _engine([wide])
+    eng.energy(pos)
+    assert eng.status() & 4
+    eng.forces(pos)
+    assert eng.status() & 4
+    compact = System(_clustered(64, 8, 10.0, 16, seed=3), beta=1.0)
+    pos2 = eng.pack([compact.R])
+    F, E = eng.forces(pos2)
+    assert eng.status() == 0
+    _assert_parity(eng, F, E, [compact], TOL64)
+
+
 @pytest.mark.parametrize("offset", [0.0, 1.0e3, -3.0e4])
 def test_translated_system(offset):
     """The exchange potential and forces are translation invariant.  For open

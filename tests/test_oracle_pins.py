@@ -328,6 +328,47 @@ def test_shift_choice_is_irrelevant(oracle_lib):
     assert _fmax_rel(a["F"], b["F"]) < 1e-11
 
 
+def _paired(npairs, P, c, D, seed):
+    """Linked pairs: the beads of particle 2i run along a segment of length c
+    from A_i to B_i and those of 2i+1 from B_i back to A_i, so each ring's
+    last bead sits on the other's first (the two-particle exchange is
+    favoured by about k c^2 over the separate rings); pairs D apart."""
+    rng = np.random.default_rng(seed)
+    R = np.zeros((2 * npairs, P, 3))
+    f = np.linspace(0.0, 1.0, P)[:, None]
+    for i in range(npairs):
+        A = np.array([D * i, 0.0, 0.0])
+        B = A + np.array([0.0, c, 0.0])
+        R[2 * i] = A + (B - A) * f
+        R[2 * i + 1] = B + (A - B) * f
+    return R + rng.normal(0.0, 0.05, R.shape)
+
+
+@pytest.mark.parametrize("c", [4.0, 8.0, 12.0, 20.0])
+def test_two_term_shift_ablation(oracle_lib, c):
+    """Appendix "Numerical Stability": any shift is exact in exact arithmetic,
+    but the simple two-term shift (E^[1,v] against V^[1,v-1] + E^[v,v]) is
+    only adequate when neither candidate lies far above the smallest term.
+    On linked pairs the smallest term of step v = 2i closes the pair, about
+    2 k c^2 below both candidates (P = 8, beta = 1, k = 4): the shifted
+    exponentials overflow double precision once beta 2 k c^2 exceeds
+    ln(DBL_MAX) ~ 709 (c = 12, 20), while the minimum shift stays at full
+    accuracy against the long-double oracle."""
+    P, beta = 8, 1.0
+    w = omega_p(P, beta)
+    R = _paired(6, P, c, 30.0, seed=1)
+    ref = oracle_lib.alg1(R, beta, 1.0, w, precision="f80", extras=False)
+    full = oracle_lib.alg1(R, beta, 1.0, w, precision="f64", shift_mode=0, extras=False)
+    two = oracle_lib.alg1(R, beta, 1.0, w, precision="f64", shift_mode=1, extras=False)
+    assert _rel(full["V"], ref["V"]) < 1e-14
+    assert _fmax_rel(full["F"], ref["F"]) < 1e-11
+    if beta * 2 * 4 * c * c > 709.8:
+        assert not math.isfinite(two["V"])
+    else:
+        assert _rel(two["V"], ref["V"]) < 1e-13
+        assert _fmax_rel(two["F"], ref["F"]) < 1e-11
+
+
 def test_long_double_agrees_with_double(oracle_lib):
     assert oracle_lib.long_double_mant_dig() >= 64
     R = cube_system(128, 8, seed=7)
