@@ -189,8 +189,12 @@ int build_tables(pimdb_t h) {
     h->n_b = (int)(b.size() + sp.size());
     h->n_s = (int)sp.size();
 
+    // MD update chunks: 8192 elements (32 per thread of a 256-thread
+    // workgroup), so a batch of a few million elements still spreads over
+    // several workgroups per CU (65536-element chunks left two thirds of the
+    // CUs idle on the 64-system batch)
     std::vector<EChunk> ec;
-    const int64_t CE = 1 << 16;
+    const int64_t CE = 1 << 13;
     for (int s = 0; s < S; ++s) {
         const int64_t b0 = h->desc[s].off, e0 = b0 + (int64_t)3 * h->desc[s].P * h->desc[s].N;
         for (int64_t x = b0; x < e0; x += CE) ec.push_back(EChunk{s, 0, x, std::min(e0, x + CE)});
