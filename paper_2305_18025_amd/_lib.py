@@ -33,6 +33,7 @@ DEBUG_FORWARD = 3
 DEBUG_BACKWARD = 4
 
 MAX_N = 4096
+MAX_BATCH = 65536
 
 _c_int, _c_i32, _c_i64 = ctypes.c_int, ctypes.c_int32, ctypes.c_int64
 _c_dbl, _c_sz, _vp = ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p

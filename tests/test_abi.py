@@ -44,6 +44,7 @@ def test_constants_match_header():
     for name in ["OK", "EINVAL", "ENOSYS", "EWORKSPACE", "EDEVICE", "ENONFINITE", "ERANGE", "FP64", "MIXED"]:
         assert getattr(_lib, "PIMDB_" + name) == d["PIMDB_" + name]
     assert _lib.MAX_N == d["PIMDB_MAX_N"]
+    assert _lib.MAX_BATCH == d["PIMDB_MAX_BATCH"]
     assert _lib.DEBUG_PROBABILITIES == d["PIMDB_DEBUG_PROBABILITIES"]
     assert _lib.DEBUG_BACKWARD == d["PIMDB_DEBUG_BACKWARD"]
     assert _lib.STATUS_RANGE == d["PIMDB_STATUS_RANGE"]

@@ -113,6 +113,37 @@ def test_uneven_batch():
     assert torch.allclose(E2, E, rtol=1e-13, atol=0)
 
 
+def test_max_batch_of_tiny_systems():
+    """The largest batch the ABI accepts (PIMDB_MAX_BATCH = 65536 systems),
+    of tiny systems (N = 1..9, P = 2..5, beta and m varied): every energy and
+    a sample of 512 force sets against the long-double oracle."""
+    from paper_2305_18025_amd import _lib
+    S = _lib.MAX_BATCH
+    rng = np.random.default_rng(17)
+    Ns = 1 + np.arange(S) % 9
+    Ps = 2 + (np.arange(S) // 9) % 4
+    betas = rng.uniform(0.5, 2.0, S)
+    ms = rng.uniform(0.5, 2.0, S)
+    Rs = [rng.normal(0.0, 1.0, (int(n), 1, 3)) + rng.normal(0.0, 0.3, (int(n), int(p), 3))
+          for n, p in zip(Ns, Ps)]
+    eng = BosonicExchange([int(n) for n in Ns], [int(p) for p in Ps], list(betas), list(ms),
+                          [omega_p(int(p), float(b)) for p, b in zip(Ps, betas)])
+    pos = eng.pack(Rs)
+    F, E = eng.forces(pos)
+    assert eng.status() == 0
+    Eh = E.cpu().numpy()
+    sample = set(rng.choice(S, 512, replace=False).tolist())
+    worst_e = worst_f = 0.0
+    for i in range(S):
+        w = omega_p(int(Ps[i]), float(betas[i]))
+        o = oracle.alg1(Rs[i], float(betas[i]), float(ms[i]), w, precision="f80", forces=i in sample, extras=False)
+        worst_e = max(worst_e, abs(Eh[i] - o["V"]) / abs(o["V"]))
+        if i in sample:
+            Fg = eng.unpack(F, i)
+            worst_f = max(worst_f, float(np.abs(Fg - o["F"]).max() / np.abs(o["F"]).max()))
+    assert worst_e <= TOL64 and worst_f <= TOL64, (worst_e, worst_f)
+
+
 def test_periodic_box():
     rng = np.random.default_rng(3)
     L = 5.0
