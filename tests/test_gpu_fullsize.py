@@ -1,6 +1,7 @@
 """GPU parity at the full workload sizes: the 64-system uneven batch
-(N up to 2048, P in {16, 32, 64}, beta in [0.5, 2]) and the periodic
-N=4096, P=64 system, against the long-double oracle."""
+(N up to 2048, P in {16, 32, 64}, beta in [0.5, 2]), the periodic
+N=4096, P=64 system and open systems at the largest accepted N, against the
+long-double oracle."""
 import concurrent.futures as cf
 import os
 
@@ -25,6 +26,28 @@ def _threads():
         return max(1, min(16, len(os.sched_getaffinity(0))))
     except AttributeError:
         return 4
+
+
+def test_open_maximum_size():
+    """Open boundaries at the largest N the ABI accepts (4096, exactly 64
+    blocks) and a ragged neighbour (4033 = 63 blocks + 1), one batch, the
+    eight-rows-per-thread kernel: unit-density cubes, P = 8."""
+    systems = [inputs.System(inputs.cube_system(4096, 8, seed=21), beta=1.0, name="open N4096"),
+               inputs.System(inputs.cube_system(4033, 8, seed=22), beta=1.5, name="open N4033")]
+    eng = BosonicExchange([s.N for s in systems], [s.P for s in systems], [s.beta for s in systems],
+                          [s.m for s in systems], [s.omegaP for s in systems])
+    assert eng.tuning[:2] == (512, 8)
+    pos = eng.pack([s.R for s in systems])
+    F, E = eng.forces(pos)
+    torch.cuda.synchronize()
+    assert eng.status() == 0
+    with cf.ThreadPoolExecutor(2) as ex:
+        refs = list(ex.map(_oracle_f80, systems))
+    for i, (s, o) in enumerate(zip(systems, refs)):
+        ee = abs(float(E[i]) - o["V"]) / abs(o["V"])
+        fe = float(np.abs(eng.unpack(F, i) - o["F"]).max() / np.abs(o["F"]).max())
+        print("%s: energy %.2e forces %.2e" % (s.name, ee, fe))
+        assert ee <= TOL64 and fe <= TOL64
 
 
 def test_uneven_batch_of_64_full_size():
