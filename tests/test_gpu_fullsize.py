@@ -15,6 +15,7 @@ from paper_2305_18025_amd import BosonicExchange, VelocityVerlet, inputs
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-10
+TOLMIX = 1e-5
 
 
 def _oracle_f80(s):
@@ -43,11 +44,22 @@ def test_open_maximum_size():
     assert eng.status() == 0
     with cf.ThreadPoolExecutor(2) as ex:
         refs = list(ex.map(_oracle_f80, systems))
+    E2 = eng.energy(pos)
+    mix = BosonicExchange([s.N for s in systems], [s.P for s in systems], [s.beta for s in systems],
+                          [s.m for s in systems], [s.omegaP for s in systems], precision="mixed")
+    Fm, Em = mix.forces(pos)
+    torch.cuda.synchronize()
+    assert mix.status() == 0
     for i, (s, o) in enumerate(zip(systems, refs)):
         ee = abs(float(E[i]) - o["V"]) / abs(o["V"])
         fe = float(np.abs(eng.unpack(F, i) - o["F"]).max() / np.abs(o["F"]).max())
-        print("%s: energy %.2e forces %.2e" % (s.name, ee, fe))
-        assert ee <= TOL64 and fe <= TOL64
+        ee2 = abs(float(E2[i]) - o["V"]) / abs(o["V"])
+        eem = abs(float(Em[i]) - o["V"]) / abs(o["V"])
+        fem = float(np.abs(mix.unpack(Fm, i) - o["F"]).max() / np.abs(o["F"]).max())
+        print("%s: energy %.2e forces %.2e energy-only %.2e; mixed energy %.2e forces %.2e"
+              % (s.name, ee, fe, ee2, eem, fem))
+        assert ee <= TOL64 and fe <= TOL64 and ee2 <= TOL64
+        assert eem <= TOLMIX and fem <= TOLMIX
 
 
 def test_uneven_batch_of_64_full_size():
@@ -83,7 +95,7 @@ def test_periodic_large_system_full_size():
     eem = abs(float(Em[0]) - o["V"]) / abs(o["V"])
     fem = float(np.abs(eng.unpack(Fm, 0) - o["F"]).max() / np.abs(o["F"]).max())
     print("  mixed: energy %.2e forces %.2e" % (eem, fem))
-    assert eem <= 1e-5 and fem <= 1e-5
+    assert eem <= TOLMIX and fem <= TOLMIX
 
 
 def test_large_system_md_graph_runs():
