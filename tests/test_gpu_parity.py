@@ -1,6 +1,6 @@
 """GPU parity: the HIP library against the CPU oracle, element by element.
 
-Tolerances (spec contract): FP64 path 1e-10 relative -- energy
+Tolerances: FP64 path 1e-10 relative -- energy
 |dV| <= 1e-10 |V|, forces max|dF| <= 1e-10 max|F|; mixed path 1e-5.  The
 reference for sizes where the FP64 oracle's own rounding approaches 1e-10 is
 the oracle built in x87 long double.
