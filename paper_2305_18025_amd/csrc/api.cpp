@@ -34,7 +34,7 @@ struct pimdb_ctx {
     int64_t ws_doubles = 0; // after the header
     int64_t st_doubles = 0;
     SysDesc *d_desc = nullptr;
-    Item *d_items = nullptr; // [fb | f | b | s] item lists back to back
+    Item *d_items = nullptr; // item lists back to back: [fb + sp | f + sp | b + sp | sp]
     int n_fb = 0, n_f = 0, n_b = 0, n_s = 0;
     EChunk *d_echunks = nullptr;
     int n_echunks = 0;
@@ -184,10 +184,6 @@ int build_tables(pimdb_t h) {
     all.insert(all.end(), b.begin(), b.end());
     all.insert(all.end(), sp.begin(), sp.end());
     all.insert(all.end(), sp.begin(), sp.end());
-    h->n_fb = (int)(fb.size() + sp.size());
-    h->n_f = (int)(f.size() + sp.size());
-    h->n_b = (int)(b.size() + sp.size());
-    h->n_s = (int)sp.size();
 
     // MD update chunks: 8192 elements (32 per thread of a 256-thread
     // workgroup), so a batch of a few million elements still spreads over
