@@ -426,14 +426,25 @@ __device__ __forceinline__ void dot_row(double kap, double x, double y, double z
 // the exponential for every row before the next), so the chains of
 // different rows interleave.  With 3 or more rows per thread they go in
 // groups of 2 (register budget: 3 waves per SIMD).
-template <bool FWD, int LO, int HI, int JJ, bool BOX, bool MIXED, bool WSUM>
-__device__ __forceinline__ void panel_step(Rows<JJ> &R, const RecCtx &c, double zl, int ze, double ux, double uy,
-                                           double uz) {
+// Rounding constant of a row with reference exponent e: 1.5 2^52 - e.  For
+// |x| < 2^51, t = x + (1.5 2^52 - e) is x rounded to an integer (to nearest
+// even, as rint) plus the constant, and the low word of t's bits is
+// round(x) - e; so t - constant recovers round(x) exactly, and adding the
+// step's exponent ze to the low word gives te - e.  This replaces rint, a
+// conversion and a saturating add per term (used where one row per thread
+// leaves the registers for the per-row constant).
+constexpr double RMAGIC = 6755399441055744.0; // 1.5 2^52
+template <int JJ>
+__device__ __forceinline__ double row_magic(const Rows<JJ> &R, int j) { return RMAGIC - (double)R.a[j].e; }
+
+template <bool FWD, int LO, int HI, int JJ, bool BOX, bool MIXED, bool WSUM, bool MAG>
+__device__ __forceinline__ void panel_step(Rows<JJ> &R, double *Me, const RecCtx &c, double zl, int ze, double ux,
+                                           double uy, double uz) {
     constexpr int GM = JJ >= 3 ? 2 : 4;
     if constexpr (HI - LO > GM) {
-        panel_step<FWD, LO, LO + GM, JJ, BOX, MIXED, WSUM>(R, c, zl, ze, ux, uy, uz);
+        panel_step<FWD, LO, LO + GM, JJ, BOX, MIXED, WSUM, MAG>(R, Me, c, zl, ze, ux, uy, uz);
         __builtin_amdgcn_sched_barrier(0);
-        panel_step<FWD, LO + GM, HI, JJ, BOX, MIXED, WSUM>(R, c, zl, ze, ux, uy, uz);
+        panel_step<FWD, LO + GM, HI, JJ, BOX, MIXED, WSUM, MAG>(R, Me, c, zl, ze, ux, uy, uz);
     } else if constexpr (HI > LO) {
         constexpr int G = HI - LO;
         constexpr bool DOT = !BOX && !MIXED;
@@ -466,8 +477,18 @@ __device__ __forceinline__ void panel_step(Rows<JJ> &R, const RecCtx &c, double 
             for (int g = 0; g < G; ++g)
                 x[g] = fma(c.kap, sqlen<MIXED>(dx[g], dy[g], dz[g]), FWD ? R.hl[LO + g] + zl : zl);
         }
+        // t = x + 1.5 2^52 - e rounds x to an integer (nearest even) and
+        // its low word is round(x) - e
+        double tm[G];
+        if constexpr (MAG) {
 #pragma unroll
-        for (int g = 0; g < G; ++g) r[g] = rint(x[g]);
+            for (int g = 0; g < G; ++g) tm[g] = x[g] + Me[LO + g];
+#pragma unroll
+            for (int g = 0; g < G; ++g) r[g] = tm[g] - Me[LO + g];
+        } else {
+#pragma unroll
+            for (int g = 0; g < G; ++g) r[g] = rint(x[g]);
+        }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             f[g] = x[g] - r[g];
@@ -481,14 +502,20 @@ __device__ __forceinline__ void panel_step(Rows<JJ> &R, const RecCtx &c, double 
         bool big = false;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            k[g] = sub_sat(add_sat(ze, (int)r[g]), R.a[LO + g].e);
+            if constexpr (MAG)
+                k[g] = (int)(uint32_t)__builtin_bit_cast(uint64_t, tm[g]) + ze;
+            else
+                k[g] = sub_sat(add_sat(ze, (int)r[g]), R.a[LO + g].e);
             big |= k[g] > RENORM;
         }
         // wave-uniform and rare (steps go largest first): a real branch, so
         // the common path carries none of the rescaling instructions
         if (__builtin_expect(__builtin_amdgcn_ballot_w64(big) != 0, 0)) {
 #pragma unroll
-            for (int g = 0; g < G; ++g) k[g] = acc_shift<WSUM>(R.a[LO + g], add_sat(ze, (int)r[g]));
+            for (int g = 0; g < G; ++g) {
+                k[g] = acc_shift<WSUM>(R.a[LO + g], add_sat(ze, (int)r[g]));
+                if constexpr (MAG) Me[LO + g] = row_magic(R, LO + g);
+            }
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) acc_add<WSUM>(R.a[LO + g], p[g], k[g], dx[g], dy[g], dz[g]);
@@ -499,7 +526,7 @@ __device__ __forceinline__ void panel_step(Rows<JJ> &R, const RecCtx &c, double 
 // blocks in the 1- and 2-row kernels run an unrolled loop; otherwise steps
 // go in pairs with two alternating sets of step values, each read one step
 // ahead, so no values are copied between iterations.
-template <bool FWD, int LO, int HI, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR>
+template <bool FWD, int LO, int HI, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool MAG>
 __device__ __forceinline__ void panel(Rows<JJ> &R, const RecCtx &c, int blk) {
     if constexpr (HI > LO) {
         constexpr bool DOT = !BOX && !MIXED;
@@ -510,6 +537,8 @@ __device__ __forceinline__ void panel(Rows<JJ> &R, const RecCtx &c, int blk) {
         // the block's steps from the last of the recursion's order to the
         // first (largest terms first); -1 .. BK: guard entries at the ends
         auto at = [&](int n) { return FWD ? nst - 1 - n : n; };
+        double Me[JJ];
+        if constexpr (MAG) Me[0] = row_magic(R, 0);
         if constexpr (UNR) {
             if (nst == BK) {
                 // full block (1- and 2-row kernels): no tail test, four steps
@@ -519,7 +548,7 @@ __device__ __forceinline__ void panel(Rows<JJ> &R, const RecCtx &c, int blk) {
                     const int ii = FWD ? BK - 1 - n : n;
                     double ux, uy, uz, uh;
                     step_point<FWD, DOT>(S, ii, ux, uy, uz, uh);
-                    panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM>(R, c, Z[ii], E[ii], ux, uy, uz);
+                    panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM, MAG>(R, Me, c, Z[ii], E[ii], ux, uy, uz);
                 }
                 return;
             }
@@ -535,13 +564,13 @@ __device__ __forceinline__ void panel(Rows<JJ> &R, const RecCtx &c, int blk) {
             step_point<FWD, DOT>(S, i, bx, by, bz, bh);
             zb = Z[i];
             eb = E[i];
-            panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM>(R, c, za, ea, ax, ay, az);
+            panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM, MAG>(R, Me, c, za, ea, ax, ay, az);
             if (n + 1 < nst) {
                 i = at(n + 2);
                 step_point<FWD, DOT>(S, i, ax, ay, az, ah);
                 za = Z[i];
                 ea = E[i];
-                panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM>(R, c, zb, eb, bx, by, bz);
+                panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM, MAG>(R, Me, c, zb, eb, bx, by, bz);
             }
         }
     }
@@ -588,7 +617,7 @@ __device__ __forceinline__ void diag_terms(const RecCtx &c, int k) {
 
 // Phase A2: wave w < KSPLIT sums the terms of its slice of block prev's
 // steps for block k's accumulators (lane i: 64 k + i) into LDS.
-template <bool FWD, bool BOX, bool MIXED, bool WSUM>
+template <bool FWD, bool BOX, bool MIXED, bool WSUM, bool MAG>
 __device__ __forceinline__ void diag_partial(const RecCtx &c, int k, int prev) {
     const int lane = c.t & 63, w = c.t >> 6;
     const int ns = c.W >= 16 ? KSPLIT : min(KSPLIT / 2, c.W);
@@ -613,11 +642,12 @@ __device__ __forceinline__ void diag_partial(const RecCtx &c, int k, int prev) {
     const double *S = stg_block(c.sm, prev);
     const double *Z = zl_block(c.sm, prev);
     const int *E = ze_block(c.sm, prev);
+    double Me[1] = {row_magic(R, 0)};
     for (int n = i0; n < i1; ++n) {
         const int i = FWD ? nst - 1 - n : n; // largest terms first, as in the panels
         double ux, uy, uz, uh;
         step_point<FWD, !BOX && !MIXED>(S, i, ux, uy, uz, uh);
-        panel_step<FWD, 0, 1, 1, BOX, MIXED, WSUM>(R, c, Z[i], E[i], ux, uy, uz);
+        panel_step<FWD, 0, 1, 1, BOX, MIXED, WSUM, MAG>(R, Me, c, Z[i], E[i], ux, uy, uz);
     }
     double *PA = c.sm + L_PA + w * 4 * BK + lane;
     PA[0] = R.a[0].A;
@@ -779,7 +809,7 @@ __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bo
 // Phase B of one wave.  Forward: live rows [LO, JJ) (blocks >= k);
 // backward: live rows [0, HI) (blocks <= k).  DG: this wave owns block k
 // (row LO forward, row HI-1 backward).
-template <bool FWD, int LO, int HI, bool DG, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR>
+template <bool FWD, int LO, int HI, bool DG, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool MAG>
 __device__ __forceinline__ void wave_iter(Rows<JJ> &R, const RecCtx &c, int k, double *zm_out, double *ze_out,
                                           double *r_out) {
     const int prev = FWD ? k - 1 : k + 1;
@@ -793,17 +823,17 @@ __device__ __forceinline__ void wave_iter(Rows<JJ> &R, const RecCtx &c, int k, d
         __builtin_amdgcn_s_setprio(0);
         if (has_prev) {
             if (FWD)
-                panel<FWD, LO + 1, HI, JJ, BOX, MIXED, WSUM, UNR>(R, c, prev);
+                panel<FWD, LO + 1, HI, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, prev);
             else
-                panel<FWD, LO, HI - 1, JJ, BOX, MIXED, WSUM, UNR>(R, c, prev);
+                panel<FWD, LO, HI - 1, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, prev);
         }
     } else {
-        if (has_prev) panel<FWD, LO, HI, JJ, BOX, MIXED, WSUM, UNR>(R, c, prev);
+        if (has_prev) panel<FWD, LO, HI, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, prev);
     }
 }
 
 // Runtime (first live row / number of live rows, owner?) -> compiled variant.
-template <bool FWD, int X, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR>
+template <bool FWD, int X, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool MAG>
 __device__ __forceinline__ void wave_dispatch(Rows<JJ> &R, const RecCtx &c, int k, int x, bool dg, double *zm_out,
                                               double *ze_out, double *r_out) {
     if constexpr (X <= JJ) {
@@ -811,25 +841,25 @@ __device__ __forceinline__ void wave_dispatch(Rows<JJ> &R, const RecCtx &c, int 
             if (FWD) {
                 if constexpr (X < JJ) {
                     if (dg)
-                        wave_iter<FWD, X, JJ, true, JJ, BOX, MIXED, WSUM, UNR>(R, c, k, zm_out, ze_out, r_out);
+                        wave_iter<FWD, X, JJ, true, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, k, zm_out, ze_out, r_out);
                     else
-                        wave_iter<FWD, X, JJ, false, JJ, BOX, MIXED, WSUM, UNR>(R, c, k, zm_out, ze_out, r_out);
+                        wave_iter<FWD, X, JJ, false, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, k, zm_out, ze_out, r_out);
                 }
             } else {
                 if constexpr (X > 0) {
                     if (dg)
-                        wave_iter<FWD, 0, X, true, JJ, BOX, MIXED, WSUM, UNR>(R, c, k, zm_out, ze_out, r_out);
+                        wave_iter<FWD, 0, X, true, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, k, zm_out, ze_out, r_out);
                     else
-                        wave_iter<FWD, 0, X, false, JJ, BOX, MIXED, WSUM, UNR>(R, c, k, zm_out, ze_out, r_out);
+                        wave_iter<FWD, 0, X, false, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, k, zm_out, ze_out, r_out);
                 }
             }
         } else {
-            wave_dispatch<FWD, X + 1, JJ, BOX, MIXED, WSUM, UNR>(R, c, k, x, dg, zm_out, ze_out, r_out);
+            wave_dispatch<FWD, X + 1, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, k, x, dg, zm_out, ze_out, r_out);
         }
     }
 }
 
-template <bool FWD, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR>
+template <bool FWD, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool MAG>
 __device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c) {
     const int t = c.t, T = c.T, N = c.N, W = c.W, w = t >> 6, nblk = c.nblk;
     const size_t NN = c.NN;
@@ -918,7 +948,7 @@ __device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDes
         diag_terms<FWD, BOX, MIXED>(c, k);
         if (has_prev) { // the longest work of phase A
             __builtin_amdgcn_s_setprio(1);
-            diag_partial<FWD, BOX, MIXED, WSUM>(c, k, prev);
+            diag_partial<FWD, BOX, MIXED, WSUM, MAG>(c, k, prev);
             __builtin_amdgcn_s_setprio(0);
         }
         if (stage) stage_store(c, nb, g);
@@ -933,7 +963,7 @@ __device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDes
             x = k < w ? 0 : min((k - w) / W + 1, JJ);
             dg = x > 0 && (x - 1) * W + w == k;
         }
-        wave_dispatch<FWD, 0, JJ, BOX, MIXED, WSUM, UNR>(R, c, k, x, dg, zm_out, ze_out, r_out);
+        wave_dispatch<FWD, 0, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, k, x, dg, zm_out, ze_out, r_out);
         __syncthreads();
     }
     if (range_bad) set_flag(a.flags, ST_RANGE);
@@ -945,7 +975,7 @@ template <int JJ, int J, bool FWD, bool BOX, bool MIXED, bool WSUM>
 __device__ __forceinline__ void rec_dispatch(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c, int jj) {
     if constexpr (JJ <= J) {
         if (jj == JJ)
-            recursion_rows<FWD, JJ, BOX, MIXED, WSUM, (J <= 2)>(a, sd, c);
+            recursion_rows<FWD, JJ, BOX, MIXED, WSUM, (J <= 2), (J == 1)>(a, sd, c);
         else
             rec_dispatch<JJ + 1, J, FWD, BOX, MIXED, WSUM>(a, sd, c, jj);
     }
