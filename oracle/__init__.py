@@ -7,10 +7,12 @@ with the GPU library and never imports it; the GPU library never imports this.
 Contents
 --------
 * ``pimdb_oracle.c`` / ``oracle_body.h`` -- plain C implementation of the
-  paper's Fast PIMD-B algorithm (appendix "Algorithm Pseudocode", Alg. 1), of
-  the original cubic algorithm (Alg. 2) and of the definitional backward
-  potentials (appendix "Connection Probabilities"), each in IEEE double
-  (``_f64``) and x87 long double (``_f80``).
+  quadratic-scaling potential and forces from the main text's defining
+  equations (cycle energies, forward and backward recurrences, connection
+  probabilities, interior and exterior bead forces), of the original cubic
+  algorithm (appendix "Algorithm Pseudocode", Alg. 2) and of the
+  definitional backward potentials (appendix "Connection Probabilities"),
+  each in IEEE double (``_f64``) and x87 long double (``_f80``).
 * ``brute``        -- brute force over all N! permutations with the
   representative map G (Methods, "Definition of G[sigma]").
 * ``compositions`` -- the recurrence expanded into the 2^(N-1) compositions
@@ -94,7 +96,8 @@ def long_double_mant_dig() -> int:
 
 def alg1(R, beta, m, omegaP, L=0.0, precision="f64", shift_mode=0, forces=True,
          extras=True):
-    """Fast PIMD-B (Alg. 1): V^[1,N], forces and intermediates.
+    """Quadratic-scaling potential and forces ("Fast PIMD-B"): V^[1,N],
+    forces and intermediates, from the main text's defining equations.
 
     Returns a dict with ``V`` (float), ``F`` (N,P,3) or None, and when
     ``extras``: ``Vf`` (N+1: V^[1,v]), ``Vb`` (N+2: V^[u,N] at index u),

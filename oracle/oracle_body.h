@@ -47,30 +47,35 @@ static void FN(disp_)(const double *R, int P, int a, int ja, int b, int jb, REAL
 }
 
 /*
- * Fast PIMD-B (Alg. 1 of the paper's appendix "Algorithm Pseudocode"),
- * taken step by step in the paper's order:
- *   1. interior spring energies E_int (Theory, "Reducing the potential",
- *      definition of E_int: springs j = 1..P-1, j = P excluded);
- *   2. cycle energies E^[u,v]: single-particle base case E^[v,v], then the
- *      incremental break-and-reform recurrence in u (same subsection);
- *   3. forward potentials V^[1,v] by the recurrence over the length of the
- *      cycle containing v (Background, recurrence for V^[1,N]), stabilised
- *      by the shift of the appendix "Numerical Stability";
- *   4. backward potentials V^[u,N] (Theory, "Connection probabilities",
- *      backward recursion with the 1/l weight on the absolute end index);
- *   5. connection probabilities: direct link Pr[l -> l+1] and cycle closing
- *      Pr[l -> u], u <= l (Methods, "Expressions for connection
- *      probabilities"); zero for u > l+1 (appendix lemma on vanishing
- *      probabilities);
- *   6. interior bead forces (Theory, "Force on interior beads");
- *   7. exterior bead forces (Theory, "Force on exterior beads") with the
- *      summation limits of Alg. 1, clamped to 1..N.
- *
- * shift_mode 0: the shift is the minimum over the terms (largest exponent
- * zero), the choice the paper uses for large systems.  shift_mode 1: the
- * simpler two-term shift the paper describes for small trapped systems.
- * Every shift is exact in exact arithmetic; they differ only in rounding
- * and in overflow behaviour.
+ * The quadratic-scaling potential and forces ("Fast PIMD-B"), computed from
+ * the defining equations of the paper's main text:
+ *   - interior spring energy E_int(l): the P-1 springs j -> j+1 of particle
+ *     l that no permutation changes (Theory, "Reducing the potential",
+ *     definition of the interior energy);
+ *   - cycle energy E^[u,v]: the energy of the ring through particles u..v,
+ *     i.e. the interior springs of each of them, the link from bead P of l
+ *     to bead 1 of l+1 for l = u..v-1, and the spring closing the ring from
+ *     bead P of v to bead 1 of u (Background, definition of the cycle
+ *     energies).  For each u the open part is summed particle by particle
+ *     as v grows and the closing spring is added on top;
+ *   - V^[1,v] from the recurrence over the length of the cycle that contains
+ *     v (Background, the recurrence defining the potential), V^[1,0] = 0;
+ *   - V^[u,N] from the backward recursion with weight 1/l on the last
+ *     particle l of the cycle that starts at u (Theory, "Connection
+ *     probabilities"), V^[N+1,N] = 0;
+ *   - every exponential sum is evaluated with a shift that is exact in exact
+ *     arithmetic (appendix "Numerical Stability"): shift_mode 0 takes the
+ *     smallest exponent of the sum (largest term 1), shift_mode 1 the two
+ *     candidates the paper uses for small trapped systems;
+ *   - Pr[l -> l+1] as the complement of the probability that l and l+1 lie
+ *     in different cycles (Theory, direct-link expression), Pr[l -> l'] for
+ *     l' <= l from the cycle-closing expression (Methods, "Expressions for
+ *     connection probabilities"), and 0 for l' > l+1 (Methods: a particle
+ *     links forward only to the next label);
+ *   - forces on interior beads from the ordinary ring-polymer expression
+ *     (Theory, "Force on interior beads"), and on beads 1 and P as the
+ *     probability-weighted sums over every possible neighbour l' = 1..N
+ *     (Theory, "Force on exterior beads").
  *
  * Outputs (all optional except V): V = V^[1,N]; F = -grad V in the
  * oracle layout; Vf[0..N] = V^[1,v]; Vb[0..N+1] with Vb[u] = V^[u,N] for
@@ -78,6 +83,22 @@ static void FN(disp_)(const double *R, int P, int a, int ja, int b, int jb, REAL
  * E[(u-1)*N + (v-1)] = E^[u,v] for u <= v (0 elsewhere); Eint[l-1].
  * Returns 0, or -1 on invalid arguments, -2 on allocation failure.
  */
+
+/* -(1/beta) ln( sum_i w_i exp(-beta x_i) ) for n exponents x and weights w,
+ * with the exponents shifted by sh before exponentiating. */
+static REAL FN(neg_log_sum_)(int n, const REAL *x, const REAL *w, REAL beta, REAL sh) {
+    REAL acc = 0;
+    for (int i = 0; i < n; ++i) acc += w[i] * EXP(-beta * (x[i] - sh));
+    return sh - LOG(acc) / beta;
+}
+
+static REAL FN(min_of_)(int n, const REAL *x) {
+    REAL s = x[0];
+    for (int i = 1; i < n; ++i)
+        if (x[i] < s) s = x[i];
+    return s;
+}
+
 int FN(orc_alg1)(int N, int P, const double *R, double beta, double m, double omegaP, double L,
                  int shift_mode, double *V_out, double *F_out, double *Vf_out, double *Vb_out,
                  double *Pr_out, double *E_out, double *Eint_out) {
@@ -85,117 +106,114 @@ int FN(orc_alg1)(int N, int P, const double *R, double beta, double m, double om
         return -1;
     const REAL b = (REAL)beta;
     const REAL Lr = (REAL)L;
-    const REAL k = (REAL)0.5 * (REAL)m * (REAL)omegaP * (REAL)omegaP;
+    const REAL k = (REAL)0.5 * (REAL)m * (REAL)omegaP * (REAL)omegaP; /* spring prefactor */
     const REAL mw2 = (REAL)m * (REAL)omegaP * (REAL)omegaP;
 
-    REAL *Eint = (REAL *)calloc((size_t)N + 1, sizeof(REAL));          /* 1-based */
-    REAL *E = (REAL *)calloc((size_t)(N + 1) * (N + 1), sizeof(REAL)); /* E[u*(N+1)+v] */
-    REAL *Vf = (REAL *)calloc((size_t)N + 1, sizeof(REAL));
+    REAL *Eint = (REAL *)calloc((size_t)N + 2, sizeof(REAL));          /* 1-based */
+    REAL *E = (REAL *)calloc((size_t)(N + 2) * (N + 2), sizeof(REAL)); /* E[u*(N+2)+v] */
+    REAL *Vf = (REAL *)calloc((size_t)N + 2, sizeof(REAL));
     REAL *Vb = (REAL *)calloc((size_t)N + 2, sizeof(REAL));
     REAL *Pr = (REAL *)calloc((size_t)(N + 2) * (N + 2), sizeof(REAL)); /* Pr[l*(N+2)+l'] */
-    REAL *terms = (REAL *)calloc((size_t)N + 1, sizeof(REAL));
-    if (!Eint || !E || !Vf || !Vb || !Pr || !terms) {
-        free(Eint); free(E); free(Vf); free(Vb); free(Pr); free(terms);
+    REAL *x = (REAL *)calloc((size_t)N + 2, sizeof(REAL));
+    REAL *w = (REAL *)calloc((size_t)N + 2, sizeof(REAL));
+    if (!Eint || !E || !Vf || !Vb || !Pr || !x || !w) {
+        free(Eint); free(E); free(Vf); free(Vb); free(Pr); free(x); free(w);
         return -2;
     }
-#define EE(u, v) E[(size_t)(u) * (N + 1) + (v)]
+#define EE(u, v) E[(size_t)(u) * (N + 2) + (v)]
 #define PR(l, lp) Pr[(size_t)(l) * (N + 2) + (lp)]
-    /* particle l (1-based) bead j (1-based) -> 0-based indices */
+    /* squared length of the spring between bead ja of particle a and bead jb
+     * of particle bb (1-based), minimum image when periodic */
 #define S2(a, ja, bb, jb) FN(dist2_)(R, P, (a) - 1, (ja) - 1, (bb) - 1, (jb) - 1, Lr)
 
-    /* 1. interior energies */
+    /* interior spring energies */
     for (int l = 1; l <= N; ++l) {
         REAL s = 0;
-        for (int j = 1; j <= P - 1; ++j) s += S2(l, j + 1, l, j);
+        for (int j = 1; j <= P - 1; ++j) s += S2(l, j, l, j + 1);
         Eint[l] = k * s;
     }
-    /* 2. cycle energies */
-    for (int v = 1; v <= N; ++v) {
-        EE(v, v) = Eint[v] + k * S2(v, P, v, 1);
-        for (int u = v - 1; u >= 1; --u) {
-            EE(u, v) = EE(u + 1, v) - k * S2(v, P, u + 1, 1) + k * S2(u, P, u + 1, 1) + Eint[u] +
-                       k * S2(v, P, u, 1);
+    /* cycle energies: ring through u..v = open chain u..v + closing spring */
+    for (int u = 1; u <= N; ++u) {
+        REAL open = 0; /* interior springs of u..v and the links u -> u+1 .. v-1 -> v */
+        for (int v = u; v <= N; ++v) {
+            if (v > u) open += k * S2(v - 1, P, v, 1);
+            open += Eint[v];
+            EE(u, v) = open + k * S2(v, P, u, 1);
         }
     }
-    /* 3. forward potentials V^[1,v], v = 1..N, V^[1,0] = 0 */
+    /* forward potentials: exp(-b V^[1,v]) = (1/v) sum_{u=1}^{v} exp(-b(V^[1,u-1] + E^[u,v])) */
     Vf[0] = 0;
     for (int v = 1; v <= N; ++v) {
-        /* term for cycle length kk: V^[1,v-kk] + E^[v-kk+1, v] */
-        for (int kk = 1; kk <= v; ++kk) terms[kk] = Vf[v - kk] + EE(v - kk + 1, v);
-        REAL sh;
-        if (shift_mode == 1) {
-            /* two-term shift: min(E^[1,v], V^[1,v-1] + E^[v,v]) */
-            sh = EE(1, v);
-            REAL t = Vf[v - 1] + EE(v, v);
-            if (t < sh) sh = t;
-        } else {
-            sh = terms[1];
-            for (int kk = 2; kk <= v; ++kk)
-                if (terms[kk] < sh) sh = terms[kk];
+        for (int u = 1; u <= v; ++u) {
+            x[u - 1] = Vf[u - 1] + EE(u, v);
+            w[u - 1] = (REAL)1 / (REAL)v;
         }
-        REAL acc = 0;
-        for (int kk = 1; kk <= v; ++kk) acc += EXP(-b * (terms[kk] - sh));
-        Vf[v] = sh - LOG(acc / (REAL)v) / b;
+        REAL sh;
+        if (shift_mode == 1) { /* the two candidates: whole ring 1..v, or v alone after V^[1,v-1] */
+            sh = x[0];
+            if (x[v - 1] < sh) sh = x[v - 1];
+        } else {
+            sh = FN(min_of_)(v, x);
+        }
+        Vf[v] = FN(neg_log_sum_)(v, x, w, b, sh);
     }
-    /* 4. backward potentials V^[u,N], u = N..1, V^[N+1,N] = 0 */
+    /* backward potentials: exp(-b V^[u,N]) = sum_{l=u}^{N} (1/l) exp(-b(E^[u,l] + V^[l+1,N])) */
     Vb[N + 1] = 0;
     for (int u = N; u >= 1; --u) {
-        for (int l = u; l <= N; ++l) terms[l] = EE(u, l) + Vb[l + 1];
-        REAL sh;
-        if (shift_mode == 1) {
-            /* two-term shift: min(E^[u,u] + V^[u+1,N], E^[u,N]) */
-            sh = EE(u, u) + Vb[u + 1];
-            if (EE(u, N) < sh) sh = EE(u, N);
-        } else {
-            sh = terms[u];
-            for (int l = u + 1; l <= N; ++l)
-                if (terms[l] < sh) sh = terms[l];
+        const int n = N - u + 1;
+        for (int l = u; l <= N; ++l) {
+            x[l - u] = EE(u, l) + Vb[l + 1];
+            w[l - u] = (REAL)1 / (REAL)l;
         }
-        REAL acc = 0;
-        for (int l = u; l <= N; ++l) acc += EXP(-b * (terms[l] - sh)) / (REAL)l;
-        Vb[u] = sh - LOG(acc) / b;
+        REAL sh;
+        if (shift_mode == 1) { /* u alone before V^[u+1,N], or the whole ring u..N */
+            sh = x[0];
+            if (x[n - 1] < sh) sh = x[n - 1];
+        } else {
+            sh = FN(min_of_)(n, x);
+        }
+        Vb[u] = FN(neg_log_sum_)(n, x, w, b, sh);
     }
     const REAL VN = Vf[N];
-    /* 5. connection probabilities */
-    for (int l = 1; l <= N - 1; ++l) PR(l, l + 1) = -EXPM1(-b * (Vf[l] + Vb[l + 1] - VN));
-    for (int lp = 1; lp <= N; ++lp)
-        for (int l = lp; l <= N; ++l)
-            PR(l, lp) = EXP(-b * (Vf[lp - 1] + EE(lp, l) + Vb[l + 1] - VN)) / (REAL)l;
+    /* connection probabilities Pr[l -> l'] for every pair */
+    for (int l = 1; l <= N; ++l) {
+        for (int lp = 1; lp <= N; ++lp) {
+            REAL p = 0;
+            if (lp == l + 1) /* 1 - exp(-b(V^[1,l] + V^[l+1,N] - V^[1,N])), as -expm1 */
+                p = -EXPM1(-b * (Vf[l] + Vb[l + 1] - VN));
+            else if (lp <= l) /* the ring lp..l closes: (1/l) exp(-b(V^[1,lp-1] + E^[lp,l] + V^[l+1,N] - V^[1,N])) */
+                p = EXP(-b * (Vf[lp - 1] + EE(lp, l) + Vb[l + 1] - VN)) / (REAL)l;
+            PR(l, lp) = p;
+        }
+    }
 
     if (F_out) {
-        /* 6. interior beads j = 2..P-1 */
         for (int l = 1; l <= N; ++l) {
+            /* interior beads: -m w^2 (2 r^j - r^{j+1} - r^{j-1}) */
             for (int j = 2; j <= P - 1; ++j) {
-                REAL d1[3], d2[3];
-                FN(disp_)(R, P, l - 1, j - 1, l - 1, j - 2, Lr, d1); /* r^j - r^{j-1} */
-                FN(disp_)(R, P, l - 1, j - 1, l - 1, j, Lr, d2);     /* r^j - r^{j+1} */
+                REAL up[3], dn[3];
+                FN(disp_)(R, P, l - 1, j - 1, l - 1, j, Lr, up);     /* r^j - r^{j+1} */
+                FN(disp_)(R, P, l - 1, j - 1, l - 1, j - 2, Lr, dn); /* r^j - r^{j-1} */
                 for (int c = 0; c < 3; ++c)
-                    F_out[(((size_t)l - 1) * P + (j - 1)) * 3 + c] = (double)(-mw2 * (d1[c] + d2[c]));
+                    F_out[(((size_t)l - 1) * P + (j - 1)) * 3 + c] = (double)(-mw2 * (up[c] + dn[c]));
             }
-        }
-        /* 7. exterior beads: j = 1 sums over predecessors l' (Pr[l' -> l]),
-         *    j = P sums over successors l' (Pr[l -> l']). */
-        for (int l = 1; l <= N; ++l) {
+            /* bead 1: its predecessor is bead P of l' with probability Pr[l' -> l];
+             * bead P: its successor is bead 1 of l' with probability Pr[l -> l'] */
             REAL f1[3] = {0, 0, 0}, fP[3] = {0, 0, 0};
-            int lo = l - 1 < 1 ? 1 : l - 1;
-            for (int lp = lo; lp <= N; ++lp) {
-                REAL pr = PR(lp, l);
-                REAL a[3], bb[3];
-                FN(disp_)(R, P, l - 1, 0, l - 1, 1, Lr, a);       /* r_l^1 - r_l^2 */
-                FN(disp_)(R, P, l - 1, 0, lp - 1, P - 1, Lr, bb); /* r_l^1 - r_l'^P */
-                for (int c = 0; c < 3; ++c) f1[c] += pr * mw2 * (a[c] + bb[c]);
-            }
-            int hi = l + 1 > N ? N : l + 1;
-            for (int lp = 1; lp <= hi; ++lp) {
-                REAL pr = PR(l, lp);
-                REAL a[3], bb[3];
-                FN(disp_)(R, P, l - 1, P - 1, l - 1, P - 2, Lr, a); /* r_l^P - r_l^{P-1} */
-                FN(disp_)(R, P, l - 1, P - 1, lp - 1, 0, Lr, bb);   /* r_l^P - r_l'^1 */
-                for (int c = 0; c < 3; ++c) fP[c] += pr * mw2 * (a[c] + bb[c]);
+            REAL in1[3], inP[3];
+            FN(disp_)(R, P, l - 1, 0, l - 1, 1, Lr, in1);     /* r_l^1 - r_l^2 */
+            FN(disp_)(R, P, l - 1, P - 1, l - 1, P - 2, Lr, inP); /* r_l^P - r_l^{P-1} */
+            for (int lp = 1; lp <= N; ++lp) {
+                REAL d[3];
+                const REAL pin = PR(lp, l), pout = PR(l, lp);
+                FN(disp_)(R, P, l - 1, 0, lp - 1, P - 1, Lr, d); /* r_l^1 - r_l'^P */
+                for (int c = 0; c < 3; ++c) f1[c] -= pin * mw2 * (in1[c] + d[c]);
+                FN(disp_)(R, P, l - 1, P - 1, lp - 1, 0, Lr, d); /* r_l^P - r_l'^1 */
+                for (int c = 0; c < 3; ++c) fP[c] -= pout * mw2 * (inP[c] + d[c]);
             }
             for (int c = 0; c < 3; ++c) {
-                F_out[(((size_t)l - 1) * P + 0) * 3 + c] = (double)(-f1[c]);
-                F_out[(((size_t)l - 1) * P + (P - 1)) * 3 + c] = (double)(-fP[c]);
+                F_out[(((size_t)l - 1) * P + 0) * 3 + c] = (double)f1[c];
+                F_out[(((size_t)l - 1) * P + (P - 1)) * 3 + c] = (double)fP[c];
             }
         }
     }
@@ -217,7 +235,7 @@ int FN(orc_alg1)(int N, int P, const double *R, double beta, double m, double om
 #undef EE
 #undef PR
 #undef S2
-    free(Eint); free(E); free(Vf); free(Vb); free(Pr); free(terms);
+    free(Eint); free(E); free(Vf); free(Vb); free(Pr); free(x); free(w);
     return 0;
 }
 
