@@ -6,7 +6,7 @@ algorithm, in 40-digit arithmetic (mpmath).  The approximation error is about
 rounding of the result, so degree 10 is the lowest degree that adds no error
 beyond the ~2 ulp of evaluating the polynomial in double by Horner's rule.
 Coefficients are printed lowest degree first, rounded to the nearest double;
-the output is pasted into kernels.hip (highest degree first).
+the output is pasted into common.h (highest degree first).
 
     python gen_exp2_coeffs.py
 """

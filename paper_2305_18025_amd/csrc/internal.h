@@ -95,7 +95,11 @@ struct LaunchArgs {
     int32_t mixed;         // 1: FP32 compensated endpoint spring lengths
 };
 
-// Kernel launch entry points (kernels.hip).
+// Kernel launch entry points (kernels.hip).  launch_exchange picks one of
+// the variants compiled from exchange_inst.hip (J accumulator rows per
+// thread, periodic box, mixed precision).
+template <int J, bool BOX, bool MIXED>
+hipError_t launch_exchange_variant(const LaunchArgs &a, int nitems, int threads, hipStream_t st);
 hipError_t launch_exchange(const LaunchArgs &a, int nitems, int threads, int per_thread, hipStream_t st);
 hipError_t launch_finalize(const LaunchArgs &a, int S, hipStream_t st);
 hipError_t launch_clear(int32_t *p, int64_t n, hipStream_t st);

@@ -1,1092 +1,11 @@
-// HIP kernels for gfx950: bosonic exchange potential V^[1,N] and bead forces.
-//
-// Method (Feldman & Hirshberg, "Quadratic Scaling Bosonic PIMD"):
-//   cycle energies E^[u,v]                      Theory, "Reducing the potential"
-//   forward  exp(-b V^[1,v]) = (1/v) sum_u exp(-b(V^[1,u-1] + E^[u,v]))
-//                                               Background, recurrence for V^[1,N]
-//   backward exp(-b V^[u,N]) = sum_l (1/l) exp(-b(E^[u,l] + V^[l+1,N]))
-//                                               Theory, "Connection probabilities"
-//   Pr[l -> l+1] = 1 - exp(-b(V^[1,l] + V^[l+1,N] - V^[1,N]))
-//   Pr[l -> u]   = (1/l) exp(-b(V^[1,u-1] + E^[u,l] + V^[l+1,N] - V^[1,N])), u <= l
-//                                               Methods, "Expressions for connection probabilities"
-//   exterior forces = Pr-weighted spring forces Theory, "Force on exterior beads"
-//
-// How this implementation evaluates it (every step is exact algebra on the
-// definitions above; only rounding differs):
-//
-// 1. Open-chain gauge.  For any constants c_l, replacing E^[u,v] by
-//    E^[u,v] - sum_{l=u}^{v} c_l and V^[1,v] by V^[1,v] - sum_{l<=v} c_l (and
-//    V^[u,N] by V^[u,N] - sum_{l>=u} c_l) leaves both recursions and every
-//    probability exponent unchanged.  With c_l = E_int(l) + lambda_l,
-//    lambda_l = s(l, l+1) for l < N and lambda_N = s(N, N), where
-//    s(a, b) = k |r_a^P - r_b^1|^2, the reduced cycle energy is simply
-//        Etilde[u,v] = s(v, u) - lambda_v,
-//    so the O(N^2) part needs only the 2N endpoint beads and no prefix sums;
-//    the interior springs enter only the energy, as the constant sum_l c_l.
-// 2. Extended-exponent numbers.  The recursions carry Z = exp(-b Vtilde) as a
-//    double mantissa times 2^(int exponent), so no log or exp of a potential
-//    is ever needed and no magnitude is lost to the size of V.  Each term
-//    K(u,v) = exp(-b Etilde[u,v]) = 2^x is formed as mantissa 2^frac(x)
-//    (own polynomial) times 2^round(x).
-// 3. Right-looking recursions, blocked.  Thread-owned accumulators: when
-//    Z_f[u-1] is known, every accumulator v >= u adds Z_f[u-1] K(u,v), and
-//    the owner of v = u then holds Z_f[u] = acc/u.  Steps go in blocks of 64:
-//    the wave owning a block's 64 accumulators runs its 64 steps serially
-//    with lane broadcasts, while the other waves add the previous block's
-//    64 terms to every later accumulator without synchronisation; two
-//    workgroup barriers per block.  The backward recursion is the same with rows and columns
-//    exchanged; forward and backward run concurrently in separate
-//    workgroups.
-// 4. Forces without materialised probabilities.  Pr[v -> u] (u <= v) is the
-//    forward term of accumulator v divided by its sum, times
-//    rho_v = Z_f[v] Z_b[v+1] / Z_f[N] = 1 - Pr[v -> v+1]; likewise the column
-//    Pr[l -> u] (l >= u) is the backward term of accumulator u over its sum,
-//    times rho_{u-1}.  Accumulating the term-weighted endpoint displacements
-//    next to the sums therefore gives sum_u Pr[v -> u] (r_v^P - r_u^1) and
-//    sum_l Pr[l -> u] (r_l^P - r_u^1) directly: the exterior-bead forces cost
-//    O(N) after the recursions instead of a third O(N^2) pass.
-//
-// Layout: positions/forces (P, 3, N) per system, bead-major SoA, packed.
+// HIP kernels for gfx950 other than the fused exchange launch (exchange.h):
+// exterior-bead forces and energies (finalize), velocity-Verlet updates,
+// status clearing, debug exports and the endpoint-spring table; and the
+// dispatcher that picks the exchange launch variant.
 
-#include "internal.h"
-
-#include <hip/hip_runtime.h>
-#include <math.h>
+#include "common.h"
 
 namespace pimdb {
-
-constexpr double LN2 = 0.6931471805599453;
-constexpr double LOG2E = 1.4426950408889634;
-constexpr double XLO = -536870912.0;     // -2^29: lower clamp of an exported term exponent
-constexpr double XHI = 268435456.0;      //  2^28: bound on h = -kappa |d_ref|^2
-constexpr int EMIN = -(1 << 30);         // exponent of an empty accumulator
-constexpr int EZ_LIM = 1 << 29;          // bound on the exponent of a published Z value
-constexpr int EMASK = -(3 << 29);        // term exponent that adds nothing (below EMIN)
-
-enum StatusBits { ST_NONFINITE_IN = 1, ST_NONFINITE_OUT = 2, ST_RANGE = 4 };
-
-// 2^f for |f| <= 1/2: degree-10 minimax polynomial (relative approximation
-// error 2.1e-16, about one rounding; coefficients from gen_exp2_coeffs.py),
-// highest degree first.  Kept in constant memory so the wave-uniform
-// coefficients live in scalar registers and every Horner step is one
-// v_fma_f64.
-constexpr int EXP2_N = 11;
-__constant__ double EXP2_C[EXP2_N] = {
-    7.037278846726901e-09,  1.0208537929657404e-07, 1.3215662835959238e-06, 1.5252658116409854e-05,
-    0.00015403529961127076, 0.0013333558228561767,  0.009618129108034596,   0.05550410866445883,
-    0.24022650695908768,    0.6931471805599497,     1.0};
-
-__device__ __forceinline__ double exp2_frac(double f) {
-    double p = EXP2_C[0];
-#pragma unroll
-    for (int i = 1; i < EXP2_N; ++i) p = fma(p, f, EXP2_C[i]);
-    return p;
-}
-
-template <bool BOX>
-__device__ __forceinline__ double mimg(double d, double box, double inv_box) {
-    if (BOX) return fma(-box, rint(d * inv_box), d);
-    return d;
-}
-
-// |d|^2 in FP32 with exact products (FMA) and compensated summation; the
-// displacement itself is formed in FP64 and rounded to FP32 once.
-__device__ __forceinline__ double sqlen_f32c(double dx, double dy, double dz) {
-#pragma clang fp contract(off)
-    const float x = (float)dx, y = (float)dy, z = (float)dz;
-    const float px = x * x, ex = fmaf(x, x, -px);
-    const float py = y * y, ey = fmaf(y, y, -py);
-    const float pz = z * z, ez = fmaf(z, z, -pz);
-    float s1 = px + py;
-    float bb = s1 - px;
-    const float e1 = (px - (s1 - bb)) + (py - bb);
-    const float s2 = s1 + pz;
-    bb = s2 - s1;
-    const float e2 = (s1 - (s2 - bb)) + (pz - bb);
-    const float lo = ((ex + ey) + ez) + (e1 + e2);
-    return (double)s2 + (double)lo;
-}
-
-template <bool MIXED>
-__device__ __forceinline__ double sqlen(double dx, double dy, double dz) {
-    if (MIXED) return sqlen_f32c(dx, dy, dz);
-    return fma(dx, dx, fma(dy, dy, dz * dz));
-}
-
-__device__ __forceinline__ double block_sum(double v, double *red) {
-    const int t = threadIdx.x, T = blockDim.x; // T is a power of two
-    red[t] = v;
-    __syncthreads();
-    for (int s = T >> 1; s > 0; s >>= 1) {
-        if (t < s) red[t] += red[t + s];
-        __syncthreads();
-    }
-    const double r = red[0];
-    __syncthreads();
-    return r;
-}
-
-__device__ __forceinline__ void set_flag(int32_t *flags, int bits) {
-    __hip_atomic_fetch_or(flags, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// ------------------------------------------------------------- recursions
-// Both recursions are blocked in BK = 64 steps (one wave's width).  Row j of
-// thread t holds accumulator q = j T + t, so block b (accumulators
-// [64 b, 64 b + 64)) is row b / W of wave b % W (W = T / 64 waves).
-// Forward, iteration k (block k = steps and accumulators [64 k, 64 k + 64)):
-//   phase A (all waves): the exponentials of block k's own triangle
-//     K(s+1, q+1), s <= q, go to LDS; block k-1's terms for block k's 64
-//     accumulators are summed in slices by 4 waves (8 in 16-wave
-//     workgroups; partial sums to LDS) while the last wave stages block
-//     k+1's endpoints;
-//   barrier;
-//   phase B: the wave owning block k merges the partial sums and runs the
-//     block's 64 steps serially: at step s each lane q >= s adds
-//     Z_f[s] K(s+1, q+1) (read from LDS), after which the owner lane q = s
-//     holds its final sum and Z_f[s+1] = sum / (s+1) reaches the other lanes
-//     by readlane.  Meanwhile every other accumulator beyond block k adds the
-//     64 terms of block k-1 (the panel), with no synchronisation;
-//   barrier.
-// The backward recursion is the mirror image (blocks descending, rows
-// q <= s, terms (Z_b[l+1]/l) K(q+1, l)).
-//
-// Open boundaries in FP64 (DOT): with coordinates taken relative to a
-// per-system origin, kappa |a - b|^2 + h = (kappa |a|^2 + h) + kappa |b|^2
-// - 2 kappa a.b, so a term's exponent is one add and three FMAs with
-// per-row and per-step constants, and the weighted displacements are
-// recovered from the weighted step points: sum t (a - b) = a sum t - sum t b.
-// The expansion's rounding is about kappa eps |extent|^2 in the exponent
-// (1e-12 relative for a cube of side 10).  Periodic systems (the minimum
-// image is per pair) and the mixed mode (FP32 pair lengths) keep the direct
-// form.
-//
-// Exponent bookkeeping: an accumulator (A, e) stands for A 2^e; a term
-// t 2^te is added as A += t 2^(te - e) while te - e <= RENORM, so A stays
-// below 2^(RENORM + 13).  A larger term first moves the reference to
-// e = te + RMARGIN (A, W scaled to match), leaving room for later terms up
-// to 2^(RENORM + RMARGIN) above it; A stays a normal number (at least
-// 2^-RMARGIN times a term), and terms more than 2^114 below the largest
-// underflow harmlessly.  In the gauge used here the terms of a row grow
-// along the recursion (Z_f gains a link-spring factor per step), so the
-// panels take the steps of each block in reverse order, largest first: the
-// reference then moves about once per block instead of every few steps.
-constexpr int BK = 64;
-constexpr int RENORM = 960;
-constexpr int RMARGIN = 960;
-constexpr int KSPLIT = 8;   // most waves that share the previous block's terms for the diagonal rows
-                            // (8 in 16-wave workgroups, else 4)
-constexpr int KTRI = BK * (BK + 1) / 2;
-
-// LDS map (doubles):
-//   [L_STG, +3*10*BS)  ring of 3 staged blocks, per particle
-//                      {x1, y1, z1, xP, yP, zP, h, Df, Db, -}: bead-1 and
-//                      bead-P points (relative to the origin in the dot
-//                      form), h = -kappa |r^P - r_ref^1|^2, and the dot
-//                      form's step constants Df = kappa |r^1|^2,
-//                      Db = kappa |r^P|^2 + h
-//   [L_ZM, +3*BS)      ring of 3 blocks of broadcast mantissas, per step
-//   [L_ZE, +3*BS/2)    matching exponents (ints)
-//   [L_ZL, +3*BS)      log2 of the mantissa plus the step's own exponent
-//                      constant (what the panel terms use)
-// Ring slots hold BS = BK + 2 entries: one guard entry on each side, so a
-// panel may read one step past either end of its block without a bounds
-// clamp (the guard values are never used).
-//   [L_KP, +KTRI)      the diagonal block's exponentials: mantissas,
-//                      packed triangle (zero-filled once, so reads past a
-//                      row's live part return finite values)
-//   [L_KN, +BK*BK/2)   their exponents (ints), full 64 x 64 rows; entries of
-//                      lanes a step does not reach hold EMASK (filled once)
-//   [L_PA, +KSPLIT*4*BK)  partial sums {A, Wx, Wy, Wz} per wave and lane
-//   [L_PE, +KSPLIT*BK/2)  their exponents (ints)
-//   [LDS_RED, +T)      block reduction scratch of the spring role (a
-//                      workgroup runs either a recursion or springs, so
-//                      this aliases the recursion regions)
-constexpr int L_STG = 0;
-constexpr int STG = 10; // doubles per staged particle
-constexpr int BS = BK + 2;
-constexpr int L_ZM = L_STG + 3 * STG * BS;
-constexpr int L_ZE = L_ZM + 3 * BS;
-constexpr int L_ZL = L_ZE + 3 * BS / 2;
-constexpr int L_KP = L_ZL + 3 * BS;
-constexpr int L_KN = L_KP + KTRI;
-constexpr int L_PA = L_KN + BK * BK / 2;
-constexpr int L_PE = L_PA + KSPLIT * 4 * BK;
-constexpr int L_END = L_PE + KSPLIT * BK / 2;
-constexpr int LDS_RED = 0;
-
-__device__ __forceinline__ double *stg_block(double *sm, int b) { return sm + L_STG + ((b % 3) * BS + 1) * STG; }
-__device__ __forceinline__ double *zm_block(double *sm, int b) { return sm + L_ZM + (b % 3) * BS + 1; }
-__device__ __forceinline__ int *ze_block(double *sm, int b) { return (int *)(sm + L_ZE) + (b % 3) * BS + 1; }
-__device__ __forceinline__ double *zl_block(double *sm, int b) { return sm + L_ZL + (b % 3) * BS + 1; }
-__device__ __forceinline__ int *kn_base(double *sm) { return (int *)(sm + L_KN); }
-__device__ __forceinline__ int *pe_base(double *sm) { return (int *)(sm + L_PE); }
-
-// Packed triangle of the diagonal block: forward row i_s holds lanes
-// [i_s, 64), backward row i_s holds lanes [0, i_s].
-template <bool FWD>
-__device__ __forceinline__ int tri_index(int is, int lane) {
-    return FWD ? is * BK - (is * (is - 1)) / 2 + (lane - is) : (is * (is + 1)) / 2 + lane;
-}
-
-__device__ __forceinline__ int add_sat(int a, int b) { return __builtin_elementwise_add_sat(a, b); }
-__device__ __forceinline__ int sub_sat(int a, int b) { return __builtin_elementwise_sub_sat(a, b); }
-
-// Accumulator of one row: A 2^e and the term-weighted displacements W 2^e.
-struct Acc {
-    double A, Wx, Wy, Wz;
-    int e;
-};
-
-// Move the reference of (A, W) to te + RMARGIN if the term t 2^te is more
-// than 2^RENORM above it; returns te - e for the (possibly new) reference.
-template <bool WSUM>
-__device__ __forceinline__ int acc_shift(Acc &r, int te) {
-    int k = sub_sat(te, r.e);
-    if (k > RENORM) {
-        const int sh = add_sat(k, RMARGIN);
-        r.A = ldexp(r.A, -sh);
-        if (WSUM) {
-            r.Wx = ldexp(r.Wx, -sh);
-            r.Wy = ldexp(r.Wy, -sh);
-            r.Wz = ldexp(r.Wz, -sh);
-        }
-        r.e = add_sat(te, RMARGIN);
-        k = -RMARGIN;
-    }
-    return k;
-}
-
-template <bool WSUM>
-__device__ __forceinline__ void acc_add(Acc &r, double t, int k, double dx, double dy, double dz) {
-    const double tn = ldexp(t, k);
-    r.A += tn;
-    if (WSUM) {
-        r.Wx = fma(tn, dx, r.Wx);
-        r.Wy = fma(tn, dy, r.Wy);
-        r.Wz = fma(tn, dz, r.Wz);
-    }
-}
-
-// Merge another accumulator into r.
-template <bool WSUM>
-__device__ __forceinline__ void acc_merge(Acc &r, const Acc &o) {
-    const int en = max(r.e, o.e);
-    const int a = sub_sat(r.e, en), b = sub_sat(o.e, en);
-    r.A = ldexp(r.A, a) + ldexp(o.A, b);
-    if (WSUM) {
-        r.Wx = ldexp(r.Wx, a) + ldexp(o.Wx, b);
-        r.Wy = ldexp(r.Wy, a) + ldexp(o.Wy, b);
-        r.Wz = ldexp(r.Wz, a) + ldexp(o.Wz, b);
-    }
-    r.e = en;
-}
-
-// log2(m) for a mantissa m in [0.5, 1): m is scaled into [1/sqrt 2, sqrt 2)
-// and ln(m) = 2 atanh(s), s = (m - 1) / (m + 1), |s| <= 0.172, summed as the
-// odd series s + s^3/3 + ... + s^21/21 (truncation below 1e-18).
-__device__ __forceinline__ double log2_mant(double m) {
-    const bool lo = m < 0.70710678118654752;
-    const double x = lo ? 2.0 * m : m;
-    const double s = (x - 1.0) / (x + 1.0), s2 = s * s;
-    double p = 1.0 / 21.0;
-#pragma unroll
-    for (int k = 9; k >= 0; --k) p = fma(p, s2, 1.0 / (double)(2 * k + 1));
-    return (2.0 * LOG2E) * (s * p) - (lo ? 1.0 : 0.0);
-}
-
-// 2^x as mantissa p in [0.7, 1.42] and integer exponent n; n saturates for
-// |x| >= 2^31 (such terms then add nothing).
-__device__ __forceinline__ void exp2x(double x, double &p, int &n) {
-    const double r = rint(x);
-    p = exp2_frac(x - r);
-    n = (int)r;
-}
-
-// K = 2^(kappa |a - b|^2 + h) and the displacement d = a - b (minimum
-// image when periodic).
-template <bool BOX, bool MIXED>
-__device__ __forceinline__ void kterm(double ax, double ay, double az, double bx, double by, double bz, double h,
-                                      double kap, double box, double ib, double &p, int &n, double &dx, double &dy,
-                                      double &dz) {
-    dx = mimg<BOX>(ax - bx, box, ib);
-    dy = mimg<BOX>(ay - by, box, ib);
-    dz = mimg<BOX>(az - bz, box, ib);
-    exp2x(fma(kap, sqlen<MIXED>(dx, dy, dz), h), p, n);
-}
-
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)b, lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Accumulator rows of one thread.  Direct form: (px, py, pz) = r_q^P and
-// hl = h_q (forward) or (px, py, pz) = r_q^1 (backward).  Dot form:
-// (px, py, pz) = -2 kappa times that point, hl = kappa |point|^2 (+ h_q
-// forward).  The accumulator's W holds sum t d (direct) or sum t b over the
-// step points b (dot).
-template <int JJ>
-struct Rows {
-    double px[JJ], py[JJ], pz[JJ], hl[JJ];
-    Acc a[JJ];
-};
-
-struct RecCtx {
-    double *sm;
-    const double *b1, *bP; // bead-1 and bead-P planes of the system
-    size_t NN;
-    int N, T, t, W, nblk;
-    double kap, box, ib;
-    double ox, oy, oz; // origin of the dot form (bead 1 of particle 0)
-    int32_t *flags;    // status word
-};
-
-// Staged data of one particle.
-struct Stage {
-    double x1, y1, z1, xP, yP, zP, h, Df, Db;
-};
-
-template <bool BOX, bool MIXED>
-__device__ __forceinline__ Stage stage_load(const RecCtx &c, int b, bool &bad) {
-    constexpr bool DOT = !BOX && !MIXED;
-    Stage g{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    const int l = b * BK + (c.t & 63);
-    if (l < c.N) {
-        const size_t NN = c.NN;
-        g.x1 = c.b1[l];
-        g.y1 = c.b1[NN + l];
-        g.z1 = c.b1[2 * NN + l];
-        g.xP = c.bP[l];
-        g.yP = c.bP[NN + l];
-        g.zP = c.bP[2 * NN + l];
-        const int r = l < c.N - 1 ? l + 1 : l;
-        g.h = -c.kap * sqlen<MIXED>(mimg<BOX>(g.xP - c.b1[r], c.box, c.ib),
-                                     mimg<BOX>(g.yP - c.b1[NN + r], c.box, c.ib),
-                                     mimg<BOX>(g.zP - c.b1[2 * NN + r], c.box, c.ib));
-        bad |= !(g.h <= XHI);
-        if (DOT) {
-            g.x1 -= c.ox;
-            g.y1 -= c.oy;
-            g.z1 -= c.oz;
-            g.xP -= c.ox;
-            g.yP -= c.oy;
-            g.zP -= c.oz;
-            g.Df = c.kap * (g.x1 * g.x1 + g.y1 * g.y1 + g.z1 * g.z1);
-            g.Db = fma(c.kap, g.xP * g.xP + g.yP * g.yP + g.zP * g.zP, g.h);
-        }
-    }
-    return g;
-}
-
-__device__ __forceinline__ void stage_store(const RecCtx &c, int b, const Stage &g) {
-    double *S = stg_block(c.sm, b) + STG * (c.t & 63);
-    S[0] = g.x1;
-    S[1] = g.y1;
-    S[2] = g.z1;
-    S[3] = g.xP;
-    S[4] = g.yP;
-    S[5] = g.zP;
-    S[6] = g.h;
-    S[7] = g.Df;
-    S[8] = g.Db;
-}
-
-// A step's data: forward the bead-1 point of u, backward the bead-P point
-// of l; h is h_l (direct form, backward), the step constant Df or Db (dot
-// form), else 0.
-template <bool FWD, bool DOT>
-__device__ __forceinline__ void step_point(const double *S, int i, double &x, double &y, double &z, double &h) {
-    const double *u = S + STG * i + (FWD ? 0 : 3);
-    x = u[0];
-    y = u[1];
-    z = u[2];
-    h = DOT ? (FWD ? u[7] : u[5]) : (FWD ? 0.0 : u[3]);
-}
-
-// The exponent constant of the step whose staged record is su: forward 0
-// (direct) or Df (dot); backward h (direct) or Db (dot).
-template <bool FWD, bool DOT>
-__device__ __forceinline__ double step_const(const double *su) {
-    return DOT ? (FWD ? su[7] : su[8]) : (FWD ? 0.0 : su[6]);
-}
-
-// Per-row constants of the dot form for the point (x, y, z) (origin
-// relative) with h (forward) or 0 (backward).
-__device__ __forceinline__ void dot_row(double kap, double x, double y, double z, double h, double &ax, double &ay,
-                                        double &az, double &cq) {
-    ax = -2.0 * kap * x;
-    ay = -2.0 * kap * y;
-    az = -2.0 * kap * z;
-    cq = fma(kap, x * x + y * y + z * z, h);
-}
-
-// Terms of one step for rows [LO, HI), formed in lockstep (each stage of
-// the exponential for every row before the next), so the chains of
-// different rows interleave.  With 3 or more rows per thread they go in
-// groups of 2 (register budget: 3 waves per SIMD).
-// Rounding constant of a row with reference exponent e: 1.5 2^52 - e.  For
-// |x| < 2^51, t = x + (1.5 2^52 - e) is x rounded to an integer (to nearest
-// even, as rint) plus the constant, and the low word of t's bits is
-// round(x) - e; so t - constant recovers round(x) exactly, and adding the
-// step's exponent ze to the low word gives te - e.  This replaces rint, a
-// conversion and a saturating add per term (used where one row per thread
-// leaves the registers for the per-row constant).
-constexpr double RMAGIC = 6755399441055744.0; // 1.5 2^52
-template <int JJ>
-__device__ __forceinline__ double row_magic(const Rows<JJ> &R, int j) { return RMAGIC - (double)R.a[j].e; }
-
-template <bool FWD, int LO, int HI, int JJ, bool BOX, bool MIXED, bool WSUM, bool MAG>
-__device__ __forceinline__ void panel_step(Rows<JJ> &R, double *Me, const RecCtx &c, double zl, int ze, double ux,
-                                           double uy, double uz) {
-    constexpr int GM = JJ >= 3 ? 2 : 4;
-    if constexpr (HI - LO > GM) {
-        panel_step<FWD, LO, LO + GM, JJ, BOX, MIXED, WSUM, MAG>(R, Me, c, zl, ze, ux, uy, uz);
-        __builtin_amdgcn_sched_barrier(0);
-        panel_step<FWD, LO + GM, HI, JJ, BOX, MIXED, WSUM, MAG>(R, Me, c, zl, ze, ux, uy, uz);
-    } else if constexpr (HI > LO) {
-        constexpr int G = HI - LO;
-        constexpr bool DOT = !BOX && !MIXED;
-        double x[G], r[G], f[G], p[G], dx[G], dy[G], dz[G];
-        int k[G];
-        if (DOT) { // exponent from the row and step constants; W sums t * (step point)
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int j = LO + g;
-                x[g] = fma(R.px[j], ux, fma(R.py[j], uy, fma(R.pz[j], uz, R.hl[j] + zl)));
-                dx[g] = ux;
-                dy[g] = uy;
-                dz[g] = uz;
-            }
-        } else {
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int j = LO + g;
-                if (FWD) {
-                    dx[g] = mimg<BOX>(R.px[j] - ux, c.box, c.ib);
-                    dy[g] = mimg<BOX>(R.py[j] - uy, c.box, c.ib);
-                    dz[g] = mimg<BOX>(R.pz[j] - uz, c.box, c.ib);
-                } else {
-                    dx[g] = mimg<BOX>(ux - R.px[j], c.box, c.ib);
-                    dy[g] = mimg<BOX>(uy - R.py[j], c.box, c.ib);
-                    dz[g] = mimg<BOX>(uz - R.pz[j], c.box, c.ib);
-                }
-            }
-#pragma unroll
-            for (int g = 0; g < G; ++g)
-                x[g] = fma(c.kap, sqlen<MIXED>(dx[g], dy[g], dz[g]), FWD ? R.hl[LO + g] + zl : zl);
-        }
-        // t = x + 1.5 2^52 - e rounds x to an integer (nearest even) and
-        // its low word is round(x) - e
-        double tm[G];
-        if constexpr (MAG) {
-#pragma unroll
-            for (int g = 0; g < G; ++g) tm[g] = x[g] + Me[LO + g];
-#pragma unroll
-            for (int g = 0; g < G; ++g) r[g] = tm[g] - Me[LO + g];
-        } else {
-#pragma unroll
-            for (int g = 0; g < G; ++g) r[g] = rint(x[g]);
-        }
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            f[g] = x[g] - r[g];
-            p[g] = EXP2_C[0];
-        }
-#pragma unroll
-        for (int i = 1; i < EXP2_N; ++i) {
-#pragma unroll
-            for (int g = 0; g < G; ++g) p[g] = fma(p[g], f[g], EXP2_C[i]);
-        }
-        bool big = false;
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            if constexpr (MAG)
-                k[g] = (int)(uint32_t)__builtin_bit_cast(uint64_t, tm[g]) + ze;
-            else
-                k[g] = sub_sat(add_sat(ze, (int)r[g]), R.a[LO + g].e);
-            big |= k[g] > RENORM;
-        }
-        // wave-uniform and rare (steps go largest first): a real branch, so
-        // the common path carries none of the rescaling instructions
-        if (__builtin_expect(__builtin_amdgcn_ballot_w64(big) != 0, 0)) {
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                k[g] = acc_shift<WSUM>(R.a[LO + g], add_sat(ze, (int)r[g]));
-                if constexpr (MAG) Me[LO + g] = row_magic(R, LO + g);
-            }
-        }
-#pragma unroll
-        for (int g = 0; g < G; ++g) acc_add<WSUM>(R.a[LO + g], p[g], k[g], dx[g], dy[g], dz[g]);
-    }
-}
-
-// Panel: rows [LO, HI) add the terms of the steps of block blk.  Full
-// blocks in the 1- and 2-row kernels run an unrolled loop; otherwise steps
-// go in pairs with two alternating sets of step values, each read one step
-// ahead, so no values are copied between iterations.
-template <bool FWD, int LO, int HI, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool MAG>
-__device__ __forceinline__ void panel(Rows<JJ> &R, const RecCtx &c, int blk) {
-    if constexpr (HI > LO) {
-        constexpr bool DOT = !BOX && !MIXED;
-        const int nst = min(BK, c.N - blk * BK);
-        const double *S = stg_block(c.sm, blk);
-        const double *Z = zl_block(c.sm, blk);
-        const int *E = ze_block(c.sm, blk);
-        // the block's steps from the last of the recursion's order to the
-        // first (largest terms first); -1 .. BK: guard entries at the ends
-        auto at = [&](int n) { return FWD ? nst - 1 - n : n; };
-        double Me[JJ];
-        if constexpr (MAG) Me[0] = row_magic(R, 0);
-        if constexpr (UNR) {
-            if (nst == BK) {
-                // full block (1- and 2-row kernels): no tail test, four steps
-                // per loop trip with immediate LDS offsets
-#pragma unroll 4
-                for (int n = 0; n < BK; ++n) {
-                    const int ii = FWD ? BK - 1 - n : n;
-                    double ux, uy, uz, uh;
-                    step_point<FWD, DOT>(S, ii, ux, uy, uz, uh);
-                    panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM, MAG>(R, Me, c, Z[ii], E[ii], ux, uy, uz);
-                }
-                return;
-            }
-        }
-        double ax, ay, az, ah, bx, by, bz, bh, za, zb;
-        int ea, eb;
-        int i = at(0);
-        step_point<FWD, DOT>(S, i, ax, ay, az, ah);
-        za = Z[i];
-        ea = E[i];
-        for (int n = 0; n < nst; n += 2) {
-            i = at(n + 1);
-            step_point<FWD, DOT>(S, i, bx, by, bz, bh);
-            zb = Z[i];
-            eb = E[i];
-            panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM, MAG>(R, Me, c, za, ea, ax, ay, az);
-            if (n + 1 < nst) {
-                i = at(n + 2);
-                step_point<FWD, DOT>(S, i, ax, ay, az, ah);
-                za = Z[i];
-                ea = E[i];
-                panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM, MAG>(R, Me, c, zb, eb, bx, by, bz);
-            }
-        }
-    }
-}
-
-// Phase A1: exponentials of block k's triangle into LDS, 2080 entries in 33
-// folded rows of 64 lanes: work row wr < 32 takes (wr, c) for lanes c >= wr
-// and (63 - wr, 63 - c) for c < wr; work row 32 takes the diagonal entries
-// of rows 32..63.  (Coordinates of the forward triangle s <= q; the
-// backward one is its mirror image.)  Wave w takes work rows w, w + W, ...
-template <bool FWD, bool BOX, bool MIXED>
-__device__ __forceinline__ void diag_terms(const RecCtx &c, int k) {
-    const int lane = c.t & 63, w = c.t >> 6;
-    const int nst = min(BK, c.N - k * BK);
-    const double *S = stg_block(c.sm, k);
-    double *KP = c.sm + L_KP;
-    int *KN = kn_base(c.sm);
-    for (int wr = w; wr <= BK / 2; wr += c.W) {
-        int r, q; // forward-triangle row (step) and column (accumulator)
-        bool ok = true;
-        if (wr < BK / 2) {
-            r = lane >= wr ? wr : BK - 1 - wr;
-            q = lane >= wr ? lane : BK - 1 - lane;
-        } else {
-            ok = lane < BK / 2;
-            r = q = BK - 1 - lane;
-        }
-        const int is = FWD ? r : BK - 1 - r;  // step
-        const int iq = FWD ? q : BK - 1 - q;  // accumulator
-        if (ok && is < nst) {
-            const double *me = S + STG * iq;
-            double ux, uy, uz, uh, p, dx, dy, dz;
-            int n;
-            step_point<FWD, false>(S, is, ux, uy, uz, uh);
-            if (FWD)
-                kterm<BOX, MIXED>(me[3], me[4], me[5], ux, uy, uz, me[6], c.kap, c.box, c.ib, p, n, dx, dy, dz);
-            else
-                kterm<BOX, MIXED>(ux, uy, uz, me[0], me[1], me[2], uh, c.kap, c.box, c.ib, p, n, dx, dy, dz);
-            KP[tri_index<FWD>(is, iq)] = p;
-            KN[is * BK + iq] = n;
-        }
-    }
-}
-
-// Phase A2: wave w < KSPLIT sums the terms of its slice of block prev's
-// steps for block k's accumulators (lane i: 64 k + i) into LDS.
-template <bool FWD, bool BOX, bool MIXED, bool WSUM, bool MAG>
-__device__ __forceinline__ void diag_partial(const RecCtx &c, int k, int prev) {
-    const int lane = c.t & 63, w = c.t >> 6;
-    const int ns = c.W >= 16 ? KSPLIT : min(KSPLIT / 2, c.W);
-    if (w >= ns) return;
-    const double *me = stg_block(c.sm, k) + STG * lane;
-    Rows<1> R;
-    if (FWD) {
-        R.px[0] = me[3];
-        R.py[0] = me[4];
-        R.pz[0] = me[5];
-        R.hl[0] = me[6];
-    } else {
-        R.px[0] = me[0];
-        R.py[0] = me[1];
-        R.pz[0] = me[2];
-        R.hl[0] = 0.0;
-    }
-    if (!BOX && !MIXED) dot_row(c.kap, R.px[0], R.py[0], R.pz[0], R.hl[0], R.px[0], R.py[0], R.pz[0], R.hl[0]);
-    R.a[0] = Acc{0.0, 0.0, 0.0, 0.0, EMIN};
-    const int nst = min(BK, c.N - prev * BK); // previous block: full except the backward top
-    const int i0 = (nst * w) / ns, i1 = (nst * (w + 1)) / ns;
-    const double *S = stg_block(c.sm, prev);
-    const double *Z = zl_block(c.sm, prev);
-    const int *E = ze_block(c.sm, prev);
-    double Me[1] = {row_magic(R, 0)};
-    for (int n = i0; n < i1; ++n) {
-        const int i = FWD ? nst - 1 - n : n; // largest terms first, as in the panels
-        double ux, uy, uz, uh;
-        step_point<FWD, !BOX && !MIXED>(S, i, ux, uy, uz, uh);
-        panel_step<FWD, 0, 1, 1, BOX, MIXED, WSUM, MAG>(R, Me, c, Z[i], E[i], ux, uy, uz);
-    }
-    double *PA = c.sm + L_PA + w * 4 * BK + lane;
-    PA[0] = R.a[0].A;
-    PA[BK] = R.a[0].Wx;
-    PA[2 * BK] = R.a[0].Wy;
-    PA[3 * BK] = R.a[0].Wz;
-    pe_base(c.sm)[w * BK + lane] = R.a[0].e;
-}
-
-// Phase B, owner wave: merge the partial sums, then run block k's steps
-// serially on row j (lane i: accumulator 64 k + i).  Afterwards every lane's
-// row is final: its published value goes to the broadcast ring for the
-// panels and its results to global memory.
-template <bool FWD, int j, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR>
-__device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bool has_prev, double *zm_out,
-                                         double *ze_out, double *r_out) {
-    const int lane = c.t & 63, q = k * BK + lane, N = c.N;
-    const size_t NN = c.NN;
-    const int nst = min(BK, N - k * BK);
-    Acc &r = R.a[j];
-    if (has_prev) {
-        const int ns = c.W >= 16 ? KSPLIT : min(KSPLIT / 2, c.W);
-        for (int w = 0; w < ns; ++w) {
-            const double *PA = c.sm + L_PA + w * 4 * BK + lane;
-            acc_merge<WSUM>(r, Acc{PA[0], PA[BK], PA[2 * BK], PA[3 * BK], pe_base(c.sm)[w * BK + lane]});
-        }
-    }
-    const double ivd = FWD ? 1.0 / (double)(q + 1) : (q > 0 ? 1.0 / (double)q : 0.0);
-    const double *S = stg_block(c.sm, k);
-    const double *KPl = c.sm + L_KP + lane;
-    const int *KNl = kn_base(c.sm) + lane;
-    const int first = FWD ? 0 : nst - 1;
-    double zm = zm_block(c.sm, k)[first];
-    int ze = ze_block(c.sm, k)[first];
-    // One step: every lane adds the term of step is (lanes the step does not
-    // reach read an EMASK exponent and add nothing; their KP reads stay
-    // inside the zero-filled triangle), then the owner (lane is) is complete
-    // and its scaled sum is broadcast.
-    auto step = [&](int is, double p, int n, double x, double y, double z) {
-        double dx = 0.0, dy = 0.0, dz = 0.0;
-        if (WSUM) {
-            if (!BOX && !MIXED) {
-                dx = x;
-                dy = y;
-                dz = z;
-            } else if (FWD) {
-                dx = mimg<BOX>(R.px[j] - x, c.box, c.ib);
-                dy = mimg<BOX>(R.py[j] - y, c.box, c.ib);
-                dz = mimg<BOX>(R.pz[j] - z, c.box, c.ib);
-            } else {
-                dx = mimg<BOX>(x - R.px[j], c.box, c.ib);
-                dy = mimg<BOX>(y - R.py[j], c.box, c.ib);
-                dz = mimg<BOX>(z - R.pz[j], c.box, c.ib);
-            }
-        }
-        const int te = add_sat(ze, n);
-        int kk = sub_sat(te, r.e);
-        if (__builtin_expect(__builtin_amdgcn_ballot_w64(kk > RENORM) != 0, 0)) kk = acc_shift<WSUM>(r, te);
-        acc_add<WSUM>(r, zm * p, kk, dx, dy, dz);
-        const double zz = r.A * ivd;
-        zm = readlane_f64(__builtin_amdgcn_frexp_mant(zz), is);
-        ze = __builtin_amdgcn_readlane(r.e + __builtin_amdgcn_frexp_exp(zz), is);
-    };
-    bool done = false;
-    if constexpr (UNR) {
-        if (nst == BK) {
-            // full block: unrolled, so every LDS offset is an immediate and
-            // the serial chain carries no address arithmetic; each step's
-            // values are read before the previous step's chain runs
-            double xs[2], ys[2], zs[2], ps[2], uh;
-            int es[2];
-            {
-                const int is = FWD ? 0 : BK - 1;
-                step_point<FWD, !BOX && !MIXED>(S, is, xs[0], ys[0], zs[0], uh);
-                ps[0] = KPl[tri_index<FWD>(is, 0)];
-                es[0] = KNl[is * BK];
-            }
-#pragma unroll
-            for (int i = 0; i < BK; ++i) {
-                const int is = FWD ? i : BK - 1 - i;
-                const int cu = i & 1, nx = cu ^ 1;
-                if (i + 1 < BK) {
-                    const int is2 = FWD ? i + 1 : BK - 2 - i;
-                    step_point<FWD, !BOX && !MIXED>(S, is2, xs[nx], ys[nx], zs[nx], uh);
-                    ps[nx] = KPl[tri_index<FWD>(is2, 0)];
-                    es[nx] = KNl[is2 * BK];
-                }
-                step(is, ps[cu], es[cu], xs[cu], ys[cu], zs[cu]);
-            }
-            done = true;
-        }
-    }
-    if (!done) {
-        // partial blocks (and the wider kernels, to bound code size): a
-        // step's values are read one step ahead so the LDS latency stays
-        // off the serial chain
-        struct DStep {
-            double p, x, y, z;
-            int n;
-        };
-        auto fetch = [&](int i) {
-            const int is = FWD ? min(i, nst - 1) : max(nst - 1 - i, 0);
-            DStep d;
-            d.p = KPl[tri_index<FWD>(is, 0)];
-            d.n = KNl[is * BK];
-            double uh;
-            step_point<FWD, !BOX && !MIXED>(S, is, d.x, d.y, d.z, uh);
-            return d;
-        };
-        DStep da = fetch(0), db;
-        for (int i = 0; i < nst; i += 2) {
-            db = fetch(i + 1);
-            step(FWD ? i : nst - 1 - i, da.p, da.n, da.x, da.y, da.z);
-            if (i + 1 < nst) {
-                da = fetch(i + 2);
-                step(FWD ? i + 1 : nst - 2 - i, db.p, db.n, db.x, db.y, db.z);
-            }
-        }
-    }
-    if (q < N) {
-        const double zz = r.A * ivd;
-        const double mz = __builtin_amdgcn_frexp_mant(zz);
-        const int ez = r.e + __builtin_amdgcn_frexp_exp(zz);
-        // the open-chain gauge carries the chain's cumulative spring
-        // exponents; beyond 2^29 binary orders they would approach the
-        // empty-accumulator sentinel, so the input is out of range
-        if (__builtin_expect(ez > EZ_LIM || ez < -EZ_LIM, 0)) set_flag(c.flags, ST_RANGE);
-        const int sp = FWD ? q + 1 : q - 1; // step that reads this value
-        if (sp >= 0 && sp < N) {
-            const double *su = stg_block(c.sm, sp / BK) + STG * (sp % BK);
-            zm_block(c.sm, sp / BK)[sp % BK] = mz;
-            ze_block(c.sm, sp / BK)[sp % BK] = ez;
-            zl_block(c.sm, sp / BK)[sp % BK] = log2_mant(mz) + step_const<FWD, !BOX && !MIXED>(su);
-        }
-        if (FWD) { // Z_f[q+1]
-            zm_out[q + 1] = mz;
-            ze_out[q + 1] = (double)ez;
-        } else { // Z_b[q+1]
-            zm_out[q + 1] = __builtin_amdgcn_frexp_mant(r.A);
-            ze_out[q + 1] = (double)(r.e + __builtin_amdgcn_frexp_exp(r.A));
-        }
-        if (WSUM) {
-            const double ia = 1.0 / r.A;
-            double mx = r.Wx * ia, my = r.Wy * ia, mz2 = r.Wz * ia;
-            if (!BOX && !MIXED) { // from the weighted mean step point
-                const double *me = S + STG * lane + (FWD ? 3 : 0);
-                const double sg = FWD ? -1.0 : 1.0;
-                mx = fma(sg, mx, FWD ? me[0] : -me[0]);
-                my = fma(sg, my, FWD ? me[1] : -me[1]);
-                mz2 = fma(sg, mz2, FWD ? me[2] : -me[2]);
-            }
-            r_out[q] = mx;
-            r_out[NN + q] = my;
-            r_out[2 * NN + q] = mz2;
-        }
-    }
-}
-
-// Phase B of one wave.  Forward: live rows [LO, JJ) (blocks >= k);
-// backward: live rows [0, HI) (blocks <= k).  DG: this wave owns block k
-// (row LO forward, row HI-1 backward).
-template <bool FWD, int LO, int HI, bool DG, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool MAG>
-__device__ __forceinline__ void wave_iter(Rows<JJ> &R, const RecCtx &c, int k, double *zm_out, double *ze_out,
-                                          double *r_out) {
-    const int prev = FWD ? k - 1 : k + 1;
-    const bool has_prev = FWD ? k > 0 : k + 1 < c.nblk;
-    if constexpr (DG) {
-        constexpr int jd = FWD ? LO : HI - 1;
-        // the serial chain is the critical path of phase B: its wave issues
-        // first whenever it is ready
-        __builtin_amdgcn_s_setprio(2);
-        diagonal<FWD, jd, JJ, BOX, MIXED, WSUM, UNR>(R, c, k, has_prev, zm_out, ze_out, r_out);
-        __builtin_amdgcn_s_setprio(0);
-        if (has_prev) {
-            if (FWD)
-                panel<FWD, LO + 1, HI, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, prev);
-            else
-                panel<FWD, LO, HI - 1, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, prev);
-        }
-    } else {
-        if (has_prev) panel<FWD, LO, HI, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, prev);
-    }
-}
-
-// Runtime (first live row / number of live rows, owner?) -> compiled variant.
-template <bool FWD, int X, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool MAG>
-__device__ __forceinline__ void wave_dispatch(Rows<JJ> &R, const RecCtx &c, int k, int x, bool dg, double *zm_out,
-                                              double *ze_out, double *r_out) {
-    if constexpr (X <= JJ) {
-        if (x == X) {
-            if (FWD) {
-                if constexpr (X < JJ) {
-                    if (dg)
-                        wave_iter<FWD, X, JJ, true, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, k, zm_out, ze_out, r_out);
-                    else
-                        wave_iter<FWD, X, JJ, false, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, k, zm_out, ze_out, r_out);
-                }
-            } else {
-                if constexpr (X > 0) {
-                    if (dg)
-                        wave_iter<FWD, 0, X, true, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, k, zm_out, ze_out, r_out);
-                    else
-                        wave_iter<FWD, 0, X, false, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, k, zm_out, ze_out, r_out);
-                }
-            }
-        } else {
-            wave_dispatch<FWD, X + 1, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, k, x, dg, zm_out, ze_out, r_out);
-        }
-    }
-}
-
-template <bool FWD, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool MAG>
-__device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c) {
-    const int t = c.t, T = c.T, N = c.N, W = c.W, w = t >> 6, nblk = c.nblk;
-    const size_t NN = c.NN;
-    double *zm_out, *ze_out, *r_out;
-    if (FWD) {
-        double *base = (a.mode & M_SAVE) ? a.state + sd.st : a.ws + sd.ws;
-        zm_out = base + ((a.mode & M_SAVE) ? StLayout::zf_m(N) : WsLayout::zf_m(N));
-        ze_out = base + ((a.mode & M_SAVE) ? StLayout::zf_e(N) : WsLayout::zf_e(N));
-        r_out = base + ((a.mode & M_SAVE) ? StLayout::rf(N) : WsLayout::rf(N));
-    } else {
-        double *base = a.ws + sd.ws;
-        zm_out = base + WsLayout::zb_m(N);
-        ze_out = base + WsLayout::zb_e(N);
-        r_out = base + WsLayout::rb(N);
-    }
-    Rows<JJ> R;
-    bool range_bad = false;
-#pragma unroll
-    for (int j = 0; j < JJ; ++j) {
-        const int q = j * T + t;
-        R.px[j] = R.py[j] = R.pz[j] = R.hl[j] = 0.0;
-        if (q < N) {
-            if (FWD) {
-                R.px[j] = c.bP[q];
-                R.py[j] = c.bP[NN + q];
-                R.pz[j] = c.bP[2 * NN + q];
-                const int r = q < N - 1 ? q + 1 : q;
-                R.hl[j] = -c.kap * sqlen<MIXED>(mimg<BOX>(R.px[j] - c.b1[r], c.box, c.ib),
-                                                 mimg<BOX>(R.py[j] - c.b1[NN + r], c.box, c.ib),
-                                                 mimg<BOX>(R.pz[j] - c.b1[2 * NN + r], c.box, c.ib));
-                range_bad |= !(R.hl[j] <= XHI);
-            } else {
-                R.px[j] = c.b1[q];
-                R.py[j] = c.b1[NN + q];
-                R.pz[j] = c.b1[2 * NN + q];
-            }
-            if (!BOX && !MIXED)
-                dot_row(c.kap, R.px[j] - c.ox, R.py[j] - c.oy, R.pz[j] - c.oz, R.hl[j], R.px[j], R.py[j], R.pz[j],
-                        R.hl[j]);
-        }
-        R.a[j] = Acc{0.0, 0.0, 0.0, 0.0, EMIN};
-    }
-    // first block staged, first broadcast value: Z_f[0] = 1 (V^[1,0] = 0),
-    // or Z_b[N+1] / N = 1 / N
-    const int b0 = FWD ? 0 : nblk - 1;
-    const int s0 = FWD ? 0 : N - 1;
-    if (w == 0) {
-        const Stage g = stage_load<BOX, MIXED>(c, b0, range_bad);
-        stage_store(c, b0, g);
-        if ((t & 63) == s0 % BK) {
-            const double z0 = FWD ? 1.0 : 1.0 / (double)N;
-            const double m0 = __builtin_amdgcn_frexp_mant(z0);
-            constexpr bool DOT = !BOX && !MIXED;
-            zm_block(c.sm, b0)[s0 % BK] = m0;
-            ze_block(c.sm, b0)[s0 % BK] = __builtin_amdgcn_frexp_exp(z0);
-            zl_block(c.sm, b0)[s0 % BK] = log2_mant(m0) + (DOT ? (FWD ? g.Df : g.Db) : (FWD ? 0.0 : g.h));
-        }
-    }
-    if (t == 0) {
-        if (FWD) {
-            zm_out[0] = 1.0;
-            ze_out[0] = 0.0;
-        } else {
-            zm_out[N + 1] = 1.0;
-            ze_out[N + 1] = 0.0;
-        }
-    }
-    // the diagonal triangle's fills (see the LDS map)
-    for (int i = t; i < BK * BK; i += T) kn_base(c.sm)[i] = EMASK;
-    for (int i = t; i < KTRI; i += T) c.sm[L_KP + i] = 0.0;
-    // loads of the rows are complete before the loop (a wait inside it would
-    // also wait for the staging loads issued there)
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    for (int it = 0; it < nblk; ++it) {
-        const int k = FWD ? it : nblk - 1 - it;
-        const int prev = FWD ? k - 1 : k + 1;
-        const bool has_prev = FWD ? k > 0 : k + 1 < nblk;
-        // phase A; the next block is staged by the last wave (its loads are
-        // issued first and land in LDS before the barrier; its ring slot last
-        // held block k-2, which is no longer read)
-        const int nb = FWD ? k + 1 : k - 1;
-        const bool stage = w == W - 1 && nb >= 0 && nb < nblk;
-        Stage g{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        if (stage) g = stage_load<BOX, MIXED>(c, nb, range_bad);
-        diag_terms<FWD, BOX, MIXED>(c, k);
-        if (has_prev) { // the longest work of phase A
-            __builtin_amdgcn_s_setprio(1);
-            diag_partial<FWD, BOX, MIXED, WSUM, MAG>(c, k, prev);
-            __builtin_amdgcn_s_setprio(0);
-        }
-        if (stage) stage_store(c, nb, g);
-        __syncthreads();
-        // phase B
-        int x;
-        bool dg;
-        if (FWD) { // first row j with j W + w >= k
-            x = k <= w ? 0 : (k - w + W - 1) / W;
-            dg = x * W + w == k;
-        } else { // number of rows j with j W + w <= k
-            x = k < w ? 0 : min((k - w) / W + 1, JJ);
-            dg = x > 0 && (x - 1) * W + w == k;
-        }
-        wave_dispatch<FWD, 0, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, k, x, dg, zm_out, ze_out, r_out);
-        __syncthreads();
-    }
-    if (range_bad) set_flag(a.flags, ST_RANGE);
-}
-
-// Dispatch on the number of rows the system needs, JJ = ceil(N / T) <= J,
-// so that no thread carries rows past the end of a smaller system.
-template <int JJ, int J, bool FWD, bool BOX, bool MIXED, bool WSUM>
-__device__ __forceinline__ void rec_dispatch(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c, int jj) {
-    if constexpr (JJ <= J) {
-        if (jj == JJ)
-            recursion_rows<FWD, JJ, BOX, MIXED, WSUM, (J <= 2), (J == 1)>(a, sd, c);
-        else
-            rec_dispatch<JJ + 1, J, FWD, BOX, MIXED, WSUM>(a, sd, c, jj);
-    }
-}
-
-template <int J, bool FWD, bool BOX, bool MIXED, bool WSUM>
-__device__ __forceinline__ void recursion_role(const LaunchArgs &a, const SysDesc sd, double *sm) {
-    RecCtx c;
-    c.sm = sm;
-    c.NN = (size_t)sd.N;
-    c.b1 = a.pos + sd.off;
-    c.bP = a.pos + sd.off + (size_t)(sd.P - 1) * 3 * c.NN;
-    c.N = sd.N;
-    c.T = blockDim.x;
-    c.t = threadIdx.x;
-    c.W = c.T / 64;
-    c.nblk = (sd.N + BK - 1) / BK;
-    c.kap = sd.kappa;
-    c.box = a.box;
-    c.ib = a.inv_box;
-    c.ox = c.b1[0];
-    c.oy = c.b1[c.NN];
-    c.oz = c.b1[2 * c.NN];
-    c.flags = a.flags;
-    const int jj = (sd.N + c.T - 1) / c.T;
-    rec_dispatch<1, J, FWD, BOX, MIXED, WSUM>(a, sd, c, jj);
-}
-
-// ---------------------------------------------------------------- springs
-// One thread per particle, loop over beads.  Interior energies E_int(l)
-// (Theory, "Reducing the potential", interior springs j = 1..P-1), interior
-// bead forces -m w_P^2 (2 r^j - r^{j+1} - r^{j-1}) for j = 2..P-1 (Theory,
-// "Force on interior beads"), and the optional trap.  In distinguishable mode
-// every ring closes on itself and all beads are written here.
-template <bool BOX, int GB>
-__device__ __forceinline__ void springs_role(const LaunchArgs &a, const SysDesc sd, int si, int chunk, double *sm) {
-    const int t = threadIdx.x, T = blockDim.x, N = sd.N, P = sd.P;
-    const size_t NN = (size_t)N;
-    const int q = chunk * T + t;
-    const bool dist = (a.mode & M_DIST) != 0;
-    const bool wf = (a.mode & M_FORCES) && a.out;
-    const double box = a.box, ib = a.inv_box;
-    const double k = sd.k, mw2 = sd.mw2;
-    const double trapc = sd.m * a.trap_w2 / (double)P; // force coefficient
-    const double scale = (a.mode & M_ADJOINT) ? -a.gscale[si] : 1.0;
-    double esum = 0.0;
-    bool bad = false;
-    if (q < N) {
-        // positions and forces never alias (part of the interface), so the
-        // loads of later beads may be issued ahead of this bead's stores
-        const double *__restrict__ p0 = a.pos + sd.off + q;
-        double *__restrict__ fo = wf ? a.out + sd.off + q : nullptr;
-        double cx = p0[0], cy = p0[NN], cz = p0[2 * NN];
-        double vx, vy, vz; // previous bead
-        if (dist) {
-            const size_t o = (size_t)(P - 1) * 3 * NN;
-            vx = p0[o];
-            vy = p0[o + NN];
-            vz = p0[o + 2 * NN];
-        } else {
-            vx = cx; vy = cy; vz = cz;
-        }
-        double ei = 0.0, et = 0.0;
-        // beads in groups of GB: the group's loads are all issued before any
-        // of its arithmetic, so the memory latency is paid once per group
-        for (int j0 = 0; j0 < P; j0 += GB) {
-            double gx[GB], gy[GB], gz[GB];
-#pragma unroll
-            for (int u = 0; u < GB; ++u) {
-                const int jn = j0 + u + 1;
-                const size_t o = (size_t)(jn < P ? jn : 0) * 3 * NN;
-                gx[u] = gy[u] = gz[u] = 0.0;
-                if (j0 + u < P) {
-                    gx[u] = p0[o];
-                    gy[u] = p0[o + NN];
-                    gz[u] = p0[o + 2 * NN];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < GB; ++u) {
-                const int j = j0 + u;
-                if (j < P) {
-                    const double nx = gx[u], ny = gy[u], nz = gz[u];
-                    bad |= !isfinite(cx) || !isfinite(cy) || !isfinite(cz);
-                    const double ax = mimg<BOX>(cx - nx, box, ib);
-                    const double ay = mimg<BOX>(cy - ny, box, ib);
-                    const double az = mimg<BOX>(cz - nz, box, ib);
-                    if (j + 1 < P || dist) ei += ax * ax + ay * ay + az * az;
-                    et += cx * cx + cy * cy + cz * cz;
-                    if (wf && ((j > 0 && j < P - 1) || dist)) {
-                        const double bx = mimg<BOX>(cx - vx, box, ib);
-                        const double by = mimg<BOX>(cy - vy, box, ib);
-                        const double bz = mimg<BOX>(cz - vz, box, ib);
-                        const size_t oj = (size_t)j * 3 * NN;
-                        // streaming stores (nothing here reads them back):
-                        // 1.3x the write bandwidth of cached stores
-                        __builtin_nontemporal_store(scale * (-mw2 * (ax + bx) - trapc * cx), fo + oj);
-                        __builtin_nontemporal_store(scale * (-mw2 * (ay + by) - trapc * cy), fo + oj + NN);
-                        __builtin_nontemporal_store(scale * (-mw2 * (az + bz) - trapc * cz), fo + oj + 2 * NN);
-                    }
-                    vx = cx; vy = cy; vz = cz;
-                    cx = nx; cy = ny; cz = nz;
-                }
-            }
-        }
-        esum = k * ei + 0.5 * trapc * et;
-    }
-    if (bad) set_flag(a.flags, ST_NONFINITE_IN);
-    const double tot = block_sum(esum, sm + LDS_RED);
-    if (t == 0) a.ws[sd.ws + WsLayout::epart(N) + chunk] = tot;
-}
 
 // ---------------------------------------------------------------- finalize
 // One workgroup per system, after the recursions.  Exterior-bead forces
@@ -1109,10 +28,13 @@ __device__ __forceinline__ void finalize(const LaunchArgs &a, const SysDesc sd, 
     const bool we = (a.mode & M_ENERGY) && a.energy;
     if (!wf && !we) return;
     const double *wsb = a.ws + sd.ws;
-    const double *fsrc = (a.mode & M_ADJOINT) ? a.state + sd.st : a.ws + sd.ws;
-    const double *zfm = fsrc + ((a.mode & M_ADJOINT) ? StLayout::zf_m(N) : WsLayout::zf_m(N));
-    const double *zfe = fsrc + ((a.mode & M_ADJOINT) ? StLayout::zf_e(N) : WsLayout::zf_e(N));
-    const double *rf = fsrc + ((a.mode & M_ADJOINT) ? StLayout::rf(N) : WsLayout::rf(N));
+    // the forward results live in the adjoint state when the forward half
+    // wrote them there (M_SAVE) or the reverse half reads them (M_ADJOINT)
+    const bool in_state = (a.mode & (M_ADJOINT | M_SAVE)) != 0;
+    const double *fsrc = in_state ? a.state + sd.st : a.ws + sd.ws;
+    const double *zfm = fsrc + (in_state ? StLayout::zf_m(N) : WsLayout::zf_m(N));
+    const double *zfe = fsrc + (in_state ? StLayout::zf_e(N) : WsLayout::zf_e(N));
+    const double *rf = fsrc + (in_state ? StLayout::rf(N) : WsLayout::rf(N));
     const double *zbm = wsb + WsLayout::zb_m(N);
     const double *zbe = wsb + WsLayout::zb_e(N);
     const double *rb = wsb + WsLayout::rb(N);
@@ -1196,42 +118,6 @@ __device__ __forceinline__ void finalize(const LaunchArgs &a, const SysDesc sd, 
     if (bad) set_flag(a.flags, ST_NONFINITE_OUT);
 }
 
-// ------------------------------------------------------------ fused kernel
-// One launch runs every recursion and spring block of the batch; the
-// exterior forces and energies follow in a second launch (k_finalize), so
-// the results of all workgroups are visible to it through the stream order
-// alone: no grid-wide flag, and no device-scope cache maintenance per
-// workgroup.
-template <int J, bool BOX, bool MIXED>
-__device__ __forceinline__ void exchange_body(const LaunchArgs &a) {
-    extern __shared__ double sm[];
-    const Item it = a.items[blockIdx.x];
-    const SysDesc sd = a.sys[it.sys];
-    if (it.role == ROLE_FORWARD) {
-        if (a.mode & M_WSUM)
-            recursion_role<J, true, BOX, MIXED, true>(a, sd, sm);
-        else
-            recursion_role<J, true, BOX, MIXED, false>(a, sd, sm);
-    } else if (it.role == ROLE_BACKWARD) {
-        recursion_role<J, false, BOX, MIXED, true>(a, sd, sm);
-    } else {
-        // 1024-thread kernels have 128 registers: smaller bead groups
-        springs_role<BOX, (J >= 4 ? 8 : 4)>(a, sd, it.sys, it.idx, sm);
-    }
-}
-
-// Register budget: J <= 2 keeps 4 waves per SIMD at 1024 threads; J = 4 and
-// J = 8 need the 512-thread bound to avoid spilling.
-template <int J, bool BOX, bool MIXED>
-__global__ void __launch_bounds__(1024) k_exchange(LaunchArgs a) {
-    exchange_body<J, BOX, MIXED>(a);
-}
-
-template <int J, bool BOX, bool MIXED>
-__global__ void __launch_bounds__(512) k_exchange_wide(LaunchArgs a) {
-    exchange_body<J, BOX, MIXED>(a);
-}
-
 // One workgroup per system (memory-latency bound: 512 threads keep twice the
 // loads of 256 in flight; at 1024 the 128-register limit makes it spill).
 constexpr int FIN_T = 512;
@@ -1251,30 +137,16 @@ hipError_t launch_finalize(const LaunchArgs &a, int S, hipStream_t st) {
     return hipGetLastError();
 }
 
-size_t exchange_smem_bytes(int threads) { return (size_t)(threads > L_END ? threads : L_END) * sizeof(double); }
-
+// ------------------------------------------------------ exchange dispatch
 template <bool BOX, bool MIXED>
 static hipError_t launch_j(const LaunchArgs &a, int nitems, int threads, int per_thread, hipStream_t st) {
-    const size_t smem = exchange_smem_bytes(threads);
     switch (per_thread) {
-    case 1:
-        hipLaunchKernelGGL((k_exchange<1, BOX, MIXED>), dim3(nitems), dim3(threads), smem, st, a);
-        break;
-    case 2:
-        hipLaunchKernelGGL((k_exchange<2, BOX, MIXED>), dim3(nitems), dim3(threads), smem, st, a);
-        break;
-    case 4:
-        if (threads > 512) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_exchange_wide<4, BOX, MIXED>), dim3(nitems), dim3(threads), smem, st, a);
-        break;
-    case 8:
-        if (threads > 512) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_exchange_wide<8, BOX, MIXED>), dim3(nitems), dim3(threads), smem, st, a);
-        break;
-    default:
-        return hipErrorInvalidValue;
+    case 1: return launch_exchange_variant<1, BOX, MIXED>(a, nitems, threads, st);
+    case 2: return launch_exchange_variant<2, BOX, MIXED>(a, nitems, threads, st);
+    case 4: return launch_exchange_variant<4, BOX, MIXED>(a, nitems, threads, st);
+    case 8: return launch_exchange_variant<8, BOX, MIXED>(a, nitems, threads, st);
+    default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_exchange(const LaunchArgs &a, int nitems, int threads, int per_thread, hipStream_t st) {

@@ -28,6 +28,24 @@ def test_adjoint_equals_minus_forces_bitwise():
     assert torch.equal(p.grad, -F)
 
 
+@pytest.mark.parametrize("before", ["fresh", "other_positions"])
+def test_potential_forward_energy_against_oracle(before):
+    """The autograd forward half returns V^[1,N] of its own positions: on a
+    fresh engine, and after a forces call on different positions (the
+    forward results of the saving call must be the ones the energy uses)."""
+    systems = [System(cube_system(n, pp, seed=n + 7), beta=b) for n, pp, b in [(300, 8, 1.0), (77, 4, 0.8)]]
+    eng, pos = _engine(systems)
+    if before == "other_positions":
+        eng.forces(pos + 0.25)
+        torch.cuda.synchronize()
+    V = exchange_potential(pos.clone().requires_grad_(True), eng).detach()
+    torch.cuda.synchronize()
+    for i, s in enumerate(systems):
+        o = oracle.alg1(s.R, s.beta, s.m, s.omegaP, precision="f80", extras=False)
+        assert abs(float(V[i]) - o["V"]) <= 1e-10 * abs(o["V"]), (i, float(V[i]), o["V"])
+    assert eng.status() == 0
+
+
 def test_adjoint_batch_weights():
     systems = [System(cube_system(n, pp, seed=n), beta=b) for n, pp, b in [(100, 4, 1.0), (333, 8, 0.7), (17, 3, 2.0)]]
     eng, pos = _engine(systems)
