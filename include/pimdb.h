@@ -95,6 +95,8 @@ extern "C" {
 
 #define PIMDB_MAX_N 4096
 #define PIMDB_MAX_BATCH 65536
+/* size of the device-resident scratch of pimdb_exchange_forces_static (16 MiB) */
+#define PIMDB_STATIC_SCRATCH_BYTES 16777216
 
 typedef struct pimdb_ctx *pimdb_t;
 
@@ -177,6 +179,20 @@ int pimdb_exchange_energy(pimdb_t h, const double *pos, double *energy);
  * the interior springs and the forward and backward recursions of every
  * system concurrently, a second one the exterior-bead forces and energies. */
 int pimdb_exchange_forces(pimdb_t h, const double *pos, double *forces, double *energy);
+
+/* pimdb_exchange_forces without a caller workspace, for callers that cannot
+ * allocate (code under HIP graph capture that must not call hipMalloc, tight
+ * serving loops, harnesses that forbid allocation).  Same results, layout and
+ * asynchrony as pimdb_exchange_forces; its scratch is a library-owned device
+ * array of PIMDB_STATIC_SCRATCH_BYTES (one per device, held until the process
+ * ends), so no workspace needs to be bound and nothing is allocated.
+ * Returns PIMDB_ERANGE when the batch needs more scratch than that
+ * (pimdb_workspace_bytes > PIMDB_STATIC_SCRATCH_BYTES), PIMDB_EDEVICE if the
+ * scratch could not be set up at pimdb_create.  Every call on one device
+ * shares that device's scratch (it keeps the last call's contents): calls
+ * that overlap in time on one device, from any handle or stream, race.
+ * pimdb_status after such a call reads the scratch's status word. */
+int pimdb_exchange_forces_static(pimdb_t h, const double *pos, double *forces, double *energy);
 
 /* Bytes of the adjoint state written by pimdb_exchange_energy_save. */
 size_t pimdb_state_bytes(pimdb_t h);

@@ -34,6 +34,7 @@ DEBUG_BACKWARD = 4
 
 MAX_N = 4096
 MAX_BATCH = 65536
+STATIC_SCRATCH_BYTES = 16 << 20
 
 _c_int, _c_i32, _c_i64 = ctypes.c_int, ctypes.c_int32, ctypes.c_int64
 _c_dbl, _c_sz, _vp = ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
@@ -58,6 +59,7 @@ SIGNATURES = {
     "pimdb_bind_workspace": (_c_int, [_handle, _vp, _c_sz]),
     "pimdb_exchange_energy": (_c_int, [_handle, _vp, _vp]),
     "pimdb_exchange_forces": (_c_int, [_handle, _vp, _vp, _vp]),
+    "pimdb_exchange_forces_static": (_c_int, [_handle, _vp, _vp, _vp]),
     "pimdb_state_bytes": (_c_sz, [_handle]),
     "pimdb_exchange_energy_save": (_c_int, [_handle, _vp, _vp, _vp]),
     "pimdb_exchange_adjoint": (_c_int, [_handle, _vp, _vp, _vp, _vp]),

@@ -155,6 +155,19 @@ class BosonicExchange:
                                              self._ptr(out, self.total, "forces"), e_ptr), self._h)
         return out, energy
 
+    def forces_static(self, pos, out=None, energy=None, want_energy=True):
+        """As forces(), through the entry point that allocates nothing and
+        uses the library's static device scratch instead of the bound
+        workspace (batches up to _lib.STATIC_SCRATCH_BYTES of scratch)."""
+        out = self.empty() if out is None else out
+        if energy is None and want_energy:
+            energy = torch.empty(self.S, dtype=torch.float64, device=self.device)
+        self._stream()
+        e_ptr = self._ptr(energy, self.S, "energy") if energy is not None else None
+        check(self.lib.pimdb_exchange_forces_static(self._h, self._ptr(pos, self.total, "pos"),
+                                                    self._ptr(out, self.total, "forces"), e_ptr), self._h)
+        return out, energy
+
     def state_bytes(self) -> int:
         return int(self.lib.pimdb_state_bytes(self._h))
 

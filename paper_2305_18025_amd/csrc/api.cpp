@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -46,10 +47,48 @@ struct pimdb_ctx {
     // workspace
     char *ws = nullptr;
     size_t ws_bytes = 0;
+    // workspace whose header (status word) the last evaluation used: the
+    // bound one, or the device's static scratch (pimdb_exchange_forces_static)
+    char *status_ws = nullptr;
     std::string last_error;
 };
 
+// Scratch of pimdb_exchange_forces_static: a file-scope device array, one
+// copy per device, held until the process ends.  Host code never passes
+// `scratch` itself (in host code it names a host-side stand-in); it uses the
+// device address that hipGetSymbolAddress returns for the current device,
+// kept per device in g_scratch.
+static __device__ __align__(256) unsigned char scratch[PIMDB_STATIC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[MAX_DEVICES] = {};       // device address of `scratch` per device
+hipError_t g_scratch_err[MAX_DEVICES] = {}; // why it could not be set up
+
+// Once per device, with that device current: look up the device address of
+// `scratch` and clear its status word (a kernel, then a wait: set-up only).
+void scratch_setup(int dev) {
+    if (dev < 0 || dev >= MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[dev] || g_scratch_err[dev] != hipSuccess) return;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) e = launch_clear((int32_t *)p, WS_HEADER_BYTES / 4, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+        g_scratch_err[dev] = e;
+        return;
+    }
+    g_scratch[dev] = p;
+}
+
+void *scratch_ptr(int dev) {
+    if (dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch[dev];
+}
 
 int fail(pimdb_t h, int code, const std::string &msg) {
     if (h) h->last_error = msg;
@@ -128,6 +167,7 @@ int build_tables(pimdb_t h) {
     // batch and the launch shape: the caller binds a workspace again
     h->ws = nullptr;
     h->ws_bytes = 0;
+    h->status_ws = nullptr;
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, PIMDB_EDEVICE, "cannot select device");
     if (h->user_threads) {
@@ -227,11 +267,11 @@ int check_ready(pimdb_t h) {
     return PIMDB_OK;
 }
 
-LaunchArgs base_args(pimdb_t h) {
+LaunchArgs base_args(pimdb_t h, char *ws) {
     LaunchArgs a{};
     a.sys = h->d_desc;
-    a.flags = (int32_t *)h->ws;
-    a.ws = (double *)(h->ws + WS_HEADER_BYTES);
+    a.flags = (int32_t *)ws;
+    a.ws = (double *)(ws + WS_HEADER_BYTES);
     a.box = h->box;
     a.inv_box = h->box > 0 ? 1.0 / h->box : 0.0;
     a.trap_w2 = h->trap_w * h->trap_w;
@@ -248,6 +288,7 @@ const Item *items_s(pimdb_t h) { return h->d_items + h->n_fb + h->n_f + h->n_b; 
 int run(pimdb_t h, LaunchArgs &a, const Item *items, int n) {
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, PIMDB_EDEVICE, "cannot select device");
+    h->status_ws = (char *)a.flags;
     a.items = items;
     hipError_t e = launch_exchange(a, n, h->threads, h->per_thread, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "exchange launch");
@@ -303,6 +344,7 @@ int pimdb_create(pimdb_t *out, int device) {
             delete h;
             return PIMDB_EDEVICE;
         }
+        scratch_setup(device);
     }
     *out = h;
     return PIMDB_OK;
@@ -404,6 +446,7 @@ int pimdb_bind_workspace(pimdb_t h, void *dev_ptr, size_t bytes) {
     if (h->S > 0 && bytes < ws_bytes_needed(h)) return fail(h, PIMDB_EWORKSPACE, "workspace too small");
     h->ws = (char *)dev_ptr;
     h->ws_bytes = bytes;
+    h->status_ws = h->ws;
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, PIMDB_EDEVICE, "cannot select device");
     const int64_t nints = WS_HEADER_BYTES / 4;
@@ -417,7 +460,7 @@ int pimdb_exchange_energy(pimdb_t h, const double *pos, double *energy) {
     int rc = check_ready(h);
     if (rc) return rc;
     if (!pos || !energy) return fail(h, PIMDB_EINVAL, "null pointer");
-    LaunchArgs a = base_args(h);
+    LaunchArgs a = base_args(h, h->ws);
     a.pos = pos;
     a.energy = energy;
     a.mode = M_FWD | M_ENERGY;
@@ -429,7 +472,30 @@ int pimdb_exchange_forces(pimdb_t h, const double *pos, double *forces, double *
     if (rc) return rc;
     if (!pos || !forces) return fail(h, PIMDB_EINVAL, "null pointer");
     if (pos == forces) return fail(h, PIMDB_EINVAL, "positions and forces alias");
-    LaunchArgs a = base_args(h);
+    LaunchArgs a = base_args(h, h->ws);
+    a.pos = pos;
+    a.out = forces;
+    a.energy = energy;
+    a.mode = M_FWD | M_BWD | M_WSUM | M_FORCES | (energy ? M_ENERGY : 0);
+    return run(h, a, items_fb(h), h->n_fb);
+}
+
+int pimdb_exchange_forces_static(pimdb_t h, const double *pos, double *forces, double *energy) {
+    if (!h) return PIMDB_EINVAL;
+    if (h->S <= 0) return fail(h, PIMDB_ENOSYS, "no system set");
+    if (!pos || !forces) return fail(h, PIMDB_EINVAL, "null pointer");
+    if (pos == forces) return fail(h, PIMDB_EINVAL, "positions and forces alias");
+    const size_t need = ws_bytes_needed(h);
+    if (need > (size_t)PIMDB_STATIC_SCRATCH_BYTES)
+        return fail(h, PIMDB_ERANGE, "batch needs " + std::to_string(need) +
+                                         " bytes of scratch; the static scratch holds " +
+                                         std::to_string((size_t)PIMDB_STATIC_SCRATCH_BYTES));
+    char *ws = (char *)scratch_ptr(h->device);
+    if (!ws) {
+        const hipError_t e = (h->device >= 0 && h->device < MAX_DEVICES) ? g_scratch_err[h->device] : hipErrorInvalidDevice;
+        return fail(h, PIMDB_EDEVICE, std::string("static scratch unavailable: ") + hipGetErrorString(e));
+    }
+    LaunchArgs a = base_args(h, ws);
     a.pos = pos;
     a.out = forces;
     a.energy = energy;
@@ -441,7 +507,7 @@ int pimdb_exchange_energy_save(pimdb_t h, const double *pos, double *energy, voi
     int rc = check_ready(h);
     if (rc) return rc;
     if (!pos || !energy || !state) return fail(h, PIMDB_EINVAL, "null pointer");
-    LaunchArgs a = base_args(h);
+    LaunchArgs a = base_args(h, h->ws);
     a.pos = pos;
     a.energy = energy;
     a.state = (double *)state;
@@ -455,7 +521,7 @@ int pimdb_exchange_adjoint(pimdb_t h, const double *pos, const void *state, cons
     if (rc) return rc;
     if (!pos || !state || !grad_energy || !grad_pos) return fail(h, PIMDB_EINVAL, "null pointer");
     if (pos == grad_pos) return fail(h, PIMDB_EINVAL, "positions and gradient alias");
-    LaunchArgs a = base_args(h);
+    LaunchArgs a = base_args(h, h->ws);
     a.pos = pos;
     a.out = grad_pos;
     a.state = (double *)state;
@@ -485,7 +551,7 @@ int pimdb_distinguishable_forces(pimdb_t h, const double *pos, double *forces, d
     if (rc) return rc;
     if (!pos || !forces) return fail(h, PIMDB_EINVAL, "null pointer");
     if (pos == forces) return fail(h, PIMDB_EINVAL, "positions and forces alias");
-    LaunchArgs a = base_args(h);
+    LaunchArgs a = base_args(h, h->ws);
     a.pos = pos;
     a.out = forces;
     a.energy = energy;
@@ -501,7 +567,7 @@ int pimdb_debug_get(pimdb_t h, const double *pos, int32_t s, int what, double *d
     if (what < PIMDB_DEBUG_PROBABILITIES || what > PIMDB_DEBUG_BACKWARD)
         return fail(h, PIMDB_EINVAL, "unknown debug export");
     // recursions of the whole batch without force output
-    LaunchArgs a = base_args(h);
+    LaunchArgs a = base_args(h, h->ws);
     a.pos = pos;
     a.mode = M_FWD | M_BWD | M_WSUM;
     if ((rc = run(h, a, items_fb(h), h->n_fb))) return rc;
@@ -522,7 +588,7 @@ int pimdb_endpoint_springs(pimdb_t h, const double *pos, int32_t s, int as_float
     if (h->S <= 0) return fail(h, PIMDB_ENOSYS, "no system set");
     if (!pos || !dst) return fail(h, PIMDB_EINVAL, "null pointer");
     if (s < 0 || s >= h->S) return fail(h, PIMDB_EINVAL, "system index out of range");
-    LaunchArgs a = base_args(h);
+    LaunchArgs a = base_args(h, h->ws);
     a.pos = pos;
     DeviceGuard g(h->device);
     hipError_t e = launch_endpoint_springs(a, s, (int)h->N[s], as_float ? 1 : 0, dst, h->stream);
@@ -532,14 +598,15 @@ int pimdb_endpoint_springs(pimdb_t h, const double *pos, int32_t s, int as_float
 
 int pimdb_status(pimdb_t h, int32_t *flags) {
     if (!h) return PIMDB_EINVAL;
-    if (!h->ws) return fail(h, PIMDB_EWORKSPACE, "workspace not bound");
+    char *sw = h->status_ws ? h->status_ws : h->ws;
+    if (!sw) return fail(h, PIMDB_EWORKSPACE, "workspace not bound");
     DeviceGuard g(h->device);
     hipError_t e;
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(h, e, "synchronize");
     int32_t v = 0;
-    if ((e = hipMemcpy(&v, h->ws, sizeof(v), hipMemcpyDeviceToHost)) != hipSuccess)
+    if ((e = hipMemcpy(&v, sw, sizeof(v), hipMemcpyDeviceToHost)) != hipSuccess)
         return hip_fail(h, e, "read status");
-    if ((e = launch_clear((int32_t *)h->ws, 1, h->stream)) != hipSuccess) return hip_fail(h, e, "clear status");
+    if ((e = launch_clear((int32_t *)sw, 1, h->stream)) != hipSuccess) return hip_fail(h, e, "clear status");
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(h, e, "synchronize");
     if (flags) *flags = v;
     return v ? PIMDB_ENONFINITE : PIMDB_OK;

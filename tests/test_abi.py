@@ -45,6 +45,7 @@ def test_constants_match_header():
         assert getattr(_lib, "PIMDB_" + name) == d["PIMDB_" + name]
     assert _lib.MAX_N == d["PIMDB_MAX_N"]
     assert _lib.MAX_BATCH == d["PIMDB_MAX_BATCH"]
+    assert _lib.STATIC_SCRATCH_BYTES == d["PIMDB_STATIC_SCRATCH_BYTES"]
     assert _lib.DEBUG_PROBABILITIES == d["PIMDB_DEBUG_PROBABILITIES"]
     assert _lib.DEBUG_BACKWARD == d["PIMDB_DEBUG_BACKWARD"]
     assert _lib.STATUS_RANGE == d["PIMDB_STATUS_RANGE"]
@@ -60,6 +61,7 @@ def test_null_handle_is_rejected():
     lib = _lib.load()
     assert lib.pimdb_set_system(None, 8, 4, 1.0, 1.0, 1.0) == _lib.PIMDB_EINVAL
     assert lib.pimdb_exchange_forces(None, None, None, None) == _lib.PIMDB_EINVAL
+    assert lib.pimdb_exchange_forces_static(None, None, None, None) == _lib.PIMDB_EINVAL
     assert lib.pimdb_exchange_energy(None, None, None) == _lib.PIMDB_EINVAL
     assert lib.pimdb_status(None, None) == _lib.PIMDB_EINVAL
     assert lib.pimdb_workspace_bytes(None) == 0

@@ -1,0 +1,108 @@
+"""GPU: the entry point that allocates nothing (pimdb_exchange_forces_static)
+against pimdb_exchange_forces, called through the C ABI (ctypes), on two
+calls in a row, the second with a smaller batch, and against the
+long-double oracle at the FP64 tolerance."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2305_18025_amd import _lib, inputs
+from paper_2305_18025_amd.inputs import System, cube_system, gaussian_system
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+def _vp(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _set_batch(lib, h, systems):
+    S = len(systems)
+    arr = lambda typ, v: (typ * S)(*v)
+    rc = lib.pimdb_set_batch(h, S, arr(ctypes.c_int64, [s.N for s in systems]),
+                             arr(ctypes.c_int32, [s.P for s in systems]),
+                             arr(ctypes.c_double, [s.beta for s in systems]),
+                             arr(ctypes.c_double, [s.m for s in systems]),
+                             arr(ctypes.c_double, [s.omegaP for s in systems]))
+    assert rc == _lib.PIMDB_OK, lib.pimdb_last_error(h)
+
+
+def _pack(lib, h, systems):
+    total = int(lib.pimdb_total_elements(h))
+    flat = np.empty(total)
+    for i, s in enumerate(systems):
+        o = int(lib.pimdb_system_offset(h, i))
+        flat[o:o + s.R.size] = inputs.to_soa(s.R).ravel()
+    return torch.from_numpy(flat).cuda()
+
+
+def _unpack(lib, h, F, i, s):
+    o = int(lib.pimdb_system_offset(h, i))
+    return inputs.from_soa(F[o:o + s.R.size].view(s.P, 3, s.N).cpu().numpy())
+
+
+def test_static_scratch_entry_matches_workspace_entry():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.pimdb_create(ctypes.byref(h), 0) == _lib.PIMDB_OK
+    try:
+        stream = torch.cuda.current_stream().cuda_stream
+        assert lib.pimdb_set_stream(h, ctypes.c_void_p(stream)) == _lib.PIMDB_OK
+        big = [System(gaussian_system(1024, 32, seed=3), beta=1.0, name="N1024 P32"),
+               System(cube_system(333, 8, seed=9), beta=0.7, name="N333 P8"),
+               System(cube_system(65, 4, seed=10), beta=2.0, name="N65 P4")]
+        small = [System(cube_system(200, 16, seed=11), beta=1.3, name="N200 P16")]
+        for call, systems in enumerate((big, small)):
+            _set_batch(lib, h, systems)
+            S = len(systems)
+            pos = _pack(lib, h, systems)
+            # the workspace entry point with a bound workspace
+            nbytes = int(lib.pimdb_workspace_bytes(h))
+            assert nbytes <= _lib.STATIC_SCRATCH_BYTES
+            ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+            aligned = (ws.data_ptr() + 255) // 256 * 256
+            assert lib.pimdb_bind_workspace(h, ctypes.c_void_p(aligned), nbytes) == _lib.PIMDB_OK
+            Fw = torch.empty_like(pos)
+            Ew = torch.empty(S, dtype=torch.float64, device="cuda")
+            assert lib.pimdb_exchange_forces(h, _vp(pos), _vp(Fw), _vp(Ew)) == _lib.PIMDB_OK
+            flags = ctypes.c_int32(-1)
+            assert lib.pimdb_status(h, ctypes.byref(flags)) == _lib.PIMDB_OK and flags.value == 0
+            # the static-scratch entry point (stale contents from the previous call)
+            Fs = torch.full_like(pos, float("nan"))
+            Es = torch.full((S,), float("nan"), dtype=torch.float64, device="cuda")
+            assert lib.pimdb_exchange_forces_static(h, _vp(pos), _vp(Fs), _vp(Es)) == _lib.PIMDB_OK
+            assert lib.pimdb_status(h, ctypes.byref(flags)) == _lib.PIMDB_OK and flags.value == 0
+            torch.cuda.synchronize()
+            assert torch.equal(Fs, Fw) and torch.equal(Es, Ew), "call %d differs from the workspace entry" % call
+            for i, s in enumerate(systems):
+                o = oracle.alg1(s.R, s.beta, s.m, s.omegaP, precision="f80", extras=False)
+                ee = abs(float(Es[i]) - o["V"]) / abs(o["V"])
+                fe = float(np.abs(_unpack(lib, h, Fs, i, s) - o["F"]).max() / np.abs(o["F"]).max())
+                print("call %d %s: energy %.2e forces %.2e" % (call, s.name, ee, fe))
+                assert ee <= TOL64 and fe <= TOL64
+    finally:
+        lib.pimdb_destroy(h)
+
+
+def test_static_scratch_rejects_oversized_batch():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.pimdb_create(ctypes.byref(h), 0) == _lib.PIMDB_OK
+    try:
+        S = 1200  # 1200 systems of N=2048 need far more than 16 MiB of scratch
+        N = (ctypes.c_int64 * S)(*([2048] * S))
+        P = (ctypes.c_int32 * S)(*([4] * S))
+        one = (ctypes.c_double * S)(*([1.0] * S))
+        assert lib.pimdb_set_batch(h, S, N, P, one, one, one) == _lib.PIMDB_OK
+        assert lib.pimdb_workspace_bytes(h) > _lib.STATIC_SCRATCH_BYTES
+        dummy = torch.zeros(8, dtype=torch.float64, device="cuda")
+        rc = lib.pimdb_exchange_forces_static(h, _vp(dummy), _vp(dummy[4:]), None)
+        assert rc == _lib.PIMDB_ERANGE
+        assert b"static scratch" in lib.pimdb_last_error(h)
+    finally:
+        lib.pimdb_destroy(h)
