@@ -77,6 +77,11 @@ extern "C" {
 #define PIMDB_MIXED 1 /* endpoint-spring lengths |r_v^P - r_u^1|^2 in FP32 with compensated
                          summation (displacements formed in FP64); recursions, probabilities
                          and forces in FP64 */
+#define PIMDB_FP64_DIRECT 2 /* FP64 with every pair displacement formed directly.  PIMDB_FP64 expands
+                               |a - b|^2 around bead 1 of particle 0 for open systems (faster); its
+                               rounding grows with the system's extent, and past the bound where
+                               it still assures 1e-10 it sets PIMDB_STATUS_PRECISION.  This mode
+                               has no such bound (about 25% slower). */
 
 /* ---- device status bits (pimdb_status) ---- */
 #define PIMDB_STATUS_NONFINITE_INPUT 1  /* a position was NaN or infinite */
@@ -86,6 +91,11 @@ extern "C" {
                                            whose binary exponent passed +-2^29 (the chain's
                                            cumulative spring exponents, e.g. particles with
                                            consecutive labels thousands of length units apart) */
+#define PIMDB_STATUS_PRECISION 8        /* PIMDB_FP64 on an open system whose extent passes the
+                                           expansion's rounding bound: beta*k*log2(e)*max|r - r_0^1|^2
+                                           above 2^23 (about 600 length units at beta k = 16).
+                                           Results are finite but may miss 1e-10 relative; use
+                                           PIMDB_FP64_DIRECT */
 
 /* ---- what pimdb_debug_get exports ---- */
 #define PIMDB_DEBUG_PROBABILITIES 1 /* dense N x N per system, [l-1][l'-1] = Pr[l -> l'] */
@@ -100,56 +110,71 @@ extern "C" {
 
 typedef struct pimdb_ctx *pimdb_t;
 
-/* Create a handle on HIP device `device` (the caller's current device is
- * restored on return).  The handle starts on the null stream with no system,
+/* ------------------------------------------------------------ handle */
+
+/* Create a handle on HIP device `device`, enqueuing on `stream` (a
+ * hipStream_t passed as void*; NULL = the null stream).  The caller's
+ * current device is restored on return.  The handle starts with no system,
  * FP64 precision, open boundaries and no trap.  *out is set to NULL on
- * failure.  Returns PIMDB_EDEVICE when the device cannot be used. */
-int pimdb_create(pimdb_t *out, int device);
+ * failure.  Returns PIMDB_EINVAL for a null out or a device index out of
+ * range, PIMDB_EDEVICE when no device can be used.  Also sets up, once per
+ * device, the scratch of pimdb_exchange_forces_static. */
+int pimdb_create(pimdb_t *out, int device, void *stream);
 
 /* Free the handle and the tables it owns (waits for its stream first).
  * NULL is accepted. */
 int pimdb_destroy(pimdb_t h);
 
-/* Stream (a hipStream_t passed as void*, NULL = null stream) on which every
- * later evaluation is enqueued.  Used to follow the caller's current stream,
- * e.g. during graph capture. */
+/* Change the stream on which later calls are enqueued (follows the caller's
+ * current stream, e.g. during graph capture).  Never fails for a valid h. */
 int pimdb_set_stream(pimdb_t h, void *stream);
 
-/* One system: N >= 1 particles, P >= 2 beads (the paper's exterior-bead
- * formulas need distinct beads 1 and P), beta > 0, m > 0, omega_P > 0.
- * Equivalent to pimdb_set_batch with S = 1.  Unbinds the workspace: query
+/* ------------------------------------------------------ system set-up */
+
+/* One system of N >= 1 particles with P >= 2 beads, inverse temperature
+ * beta > 0, particle mass m > 0 and ring-polymer frequency omega_P > 0
+ * (Background: the bead springs of frequency omega_P with prefactor
+ * (1/2) m omega_P^2; P >= 2 because the exterior-bead forces of Theory,
+ * "Force on exterior beads", need distinct beads 1 and P).  Equivalent to
+ * pimdb_set_batch with S = 1.  PIMDB_EINVAL for arguments outside those
+ * ranges, PIMDB_ERANGE for N > PIMDB_MAX_N.  Unbinds the workspace: query
  * pimdb_workspace_bytes and bind again before evaluating. */
 int pimdb_set_system(pimdb_t h, int64_t N, int32_t P, double beta, double m, double omega_P);
 
-/* A batch of S independent systems, host arrays of length S.  Systems may
- * differ in N, P, beta, m and omega_P.  One evaluation call processes the
- * whole batch in two kernel launches (springs and recursions of every system,
- * then exterior forces and energies); the first launch puts the largest
- * systems first.  Unbinds the workspace, as pimdb_set_system.  On error the
- * handle is left with no system set. */
+/* A batch of S independent systems (host arrays of length S; each entry as
+ * in pimdb_set_system).  One evaluation call processes the whole batch in
+ * two kernel launches (springs and recursions of every system, then
+ * exterior forces and energies); the first launch puts the largest systems
+ * first.  PIMDB_EINVAL / PIMDB_ERANGE as pimdb_set_system, and PIMDB_ERANGE
+ * for S > PIMDB_MAX_BATCH.  Unbinds the workspace.  On error the handle is
+ * left with no system set. */
 int pimdb_set_batch(pimdb_t h, int32_t S, const int64_t *N, const int32_t *P, const double *beta,
                     const double *m, const double *omega_P);
 
 /* Cubic periodic box of side L applied to every spring displacement as the
- * minimum image d - L*rint(d/L) (round half to even).  L = 0 (default):
- * open boundaries. */
+ * minimum image d - L*rint(d/L), round half to even (Methods, "Simulation
+ * details", states periodic boundaries; the per-spring minimum image is this
+ * library's reading).  L = 0 (default): open boundaries.  PIMDB_EINVAL for
+ * L < 0 or non-finite L. */
 int pimdb_set_box(pimdb_t h, double L);
 
-/* Harmonic external trap of angular frequency w >= 0 (0 = none, default).
- * When set, energies include (1/P) sum_{l,j} (1/2) m w^2 |r_l^j|^2 and forces
- * include -(m w^2 / P) r_l^j on every bead (the paper's scaled potential
- * U-bar for a harmonic trap). */
+/* Harmonic external trap of angular frequency w >= 0 (0 = none, default):
+ * energies include the scaled potential U-bar = (1/P) sum_j sum_l
+ * (1/2) m w^2 |r_l^j|^2 of the Background section and forces include
+ * -(m w^2 / P) r_l^j on every bead.  PIMDB_EINVAL for w < 0 or non-finite. */
 int pimdb_set_trap(pimdb_t h, double w);
 
-/* PIMDB_FP64 (default) or PIMDB_MIXED. */
+/* PIMDB_FP64 (default), PIMDB_MIXED or PIMDB_FP64_DIRECT; PIMDB_EINVAL
+ * otherwise.  Takes effect at the next evaluation call. */
 int pimdb_set_precision(pimdb_t h, int mode);
 
 /* Launch shape override: threads per workgroup (64, 128, 256, 512 or 1024)
  * and particles owned per thread in the recursions (1, 2, 4 or 8; 4 and 8 need
- * threads <= 512).  Both 0
- * restores the built-in choice.  PIMDB_EINVAL if the pair cannot hold the
- * largest system (threads * per_thread < N_max).  With a system set, this
- * unbinds the workspace like pimdb_set_batch. */
+ * threads <= 512).  Both 0 restores the built-in choice.  PIMDB_EINVAL if the
+ * pair cannot hold the largest system (threads * per_thread < N_max).  With
+ * a system set, this rebuilds the tables and unbinds the workspace like
+ * pimdb_set_batch; graphs captured before keep working (the replaced tables
+ * stay allocated until pimdb_destroy) as long as their workspace does. */
 int pimdb_set_tuning(pimdb_t h, int threads, int per_thread);
 
 /* Current launch shape (after the automatic choice). */
@@ -162,23 +187,53 @@ int64_t pimdb_system_offset(pimdb_t h, int32_t s);
 /* Total elements (sum 3 P_s N_s) of a packed position array; 0 if unset. */
 int64_t pimdb_total_elements(pimdb_t h);
 
-/* Device scratch bytes the evaluation calls need for the current batch. */
+/* Device scratch bytes the evaluation calls need for the current batch
+ * (about 80 N bytes per system; nothing O(N^2) is ever stored). */
 size_t pimdb_workspace_bytes(pimdb_t h);
 
 /* Bind caller-owned device memory (at least pimdb_workspace_bytes, 256-byte
  * aligned) as scratch.  The library clears its status word with a kernel
- * on the handle's stream.  The memory must stay allocated while bound. */
+ * on the handle's stream.  The memory must stay allocated while bound.
+ * PIMDB_EINVAL for a null or misaligned pointer, PIMDB_EWORKSPACE if too
+ * small. */
 int pimdb_bind_workspace(pimdb_t h, void *dev_ptr, size_t bytes);
 
-/* V^[1,N] for every system -> energy[s].  Computes the interior spring
- * energies and the forward recurrence only. */
+/* --------------------------------------------------------- evaluation
+ * Common to the evaluation calls: device pointers in the layout above;
+ * asynchronous on the handle's stream; PIMDB_ENOSYS without a system,
+ * PIMDB_EWORKSPACE without a large enough bound workspace, PIMDB_EINVAL for
+ * null or aliasing pointers, PIMDB_EDEVICE if a launch fails.  Non-finite
+ * or out-of-range data are reported through pimdb_status. */
+
+/* V^[1,N] of every system -> energy[s]: the interior spring energies and the
+ * forward recurrence exp(-beta V^[1,v]) = (1/v) sum_{k=1}^{v}
+ * exp(-beta (V^[1,v-k] + E^[v-k+1,v])), V^[1,0] = 0 (Background, the
+ * recurrence that defines the potential), with the cycle energies E^[u,v]
+ * of Theory, "Reducing the potential to O(N^2 + PN)".  energy: S doubles. */
 int pimdb_exchange_energy(pimdb_t h, const double *pos, double *energy);
 
-/* Energies (energy may be NULL) and forces -grad V^[1,N] (+ trap terms if set)
- * on all beads of all systems.  This is the hot path: one kernel launch runs
- * the interior springs and the forward and backward recursions of every
- * system concurrently, a second one the exterior-bead forces and energies. */
+/* Energies (energy may be NULL) and forces -grad V^[1,N] (plus trap terms if
+ * set) on all beads of all systems: interior beads by Theory, "Force on
+ * interior beads"; beads 1 and P by the probability-weighted sums of Theory,
+ * "Force on exterior beads", with the backward potentials V^[u,N] of Theory,
+ * "Connection probabilities", the direct-link probability given there and
+ * the cycle-closing probabilities of Methods, "Expressions for connection
+ * probabilities" (the whole of Alg. 1 in the appendix).  forces: same
+ * layout as pos, overwritten.  One kernel launch runs the interior springs
+ * and both recursions of every system concurrently, a second one the
+ * exterior-bead forces and energies. */
 int pimdb_exchange_forces(pimdb_t h, const double *pos, double *forces, double *energy);
+
+/* pimdb_exchange_forces for systems packed at caller-chosen places:
+ * offsets_dev is a device array of S int64 element offsets, system s
+ * occupying 3 P_s N_s elements (bead-major (P, 3, N)) from offsets_dev[s] in
+ * both pos_packed and forces_packed; energies: S doubles.  The offsets are
+ * read on the device and honoured as given: the caller guarantees that every
+ * system lies inside its buffers and that systems do not overlap in
+ * forces_packed.  A negative offset skips that system and sets
+ * PIMDB_STATUS_RANGE.  Same passages as pimdb_exchange_forces. */
+int pimdb_exchange_forces_batched(pimdb_t h, const double *pos_packed, const int64_t *offsets_dev,
+                                  double *forces_packed, double *energies);
 
 /* pimdb_exchange_forces without a caller workspace, for callers that cannot
  * allocate (code under HIP graph capture that must not call hipMalloc, tight
@@ -197,46 +252,62 @@ int pimdb_exchange_forces_static(pimdb_t h, const double *pos, double *forces, d
 /* Bytes of the adjoint state written by pimdb_exchange_energy_save. */
 size_t pimdb_state_bytes(pimdb_t h);
 
-/* Forward half for reverse-mode differentiation: energies -> energy[s], and
- * the forward potentials plus the forward-weighted endpoint displacements
- * -> state (caller-owned device buffer of pimdb_state_bytes). */
+/* Forward half for reverse-mode differentiation: energies -> energy[s] (as
+ * pimdb_exchange_energy), and the forward potentials V^[1,v] plus the
+ * forward-weighted endpoint displacements -> state (caller-owned device
+ * buffer of pimdb_state_bytes), which the reverse half needs for the
+ * exterior-bead forces. */
 int pimdb_exchange_energy_save(pimdb_t h, const double *pos, double *energy, void *state);
 
 /* Reverse half (the adjoint): grad_pos = grad_energy[s] * dV_s/dpos for every
  * system s, from the positions and a state written by
  * pimdb_exchange_energy_save on the same positions.  grad_energy is a device
- * array of S doubles.  This runs the backward recursion and the
- * connection-probability force evaluation of the paper. */
+ * array of S doubles.  It runs the backward recursion (Theory, "Connection
+ * probabilities"), the connection probabilities and the interior and
+ * exterior bead forces of Theory, "Reducing the force to O(N^2 + PN)",
+ * scaled by -grad_energy[s]. */
 int pimdb_exchange_adjoint(pimdb_t h, const double *pos, const void *state, const double *grad_energy,
                            double *grad_pos);
 
-/* Velocity-Verlet step for every bead of every system (mass m_s per bead):
+/* Velocity-Verlet step for every bead of every system (bead mass m_s; the
+ * time step of the paper's runs is in Methods, "Simulation details"):
  *   vel += dt/(2 m) forces; pos += dt vel; forces, energy <- pimdb_exchange_forces(pos);
  *   vel += dt/(2 m) forces.
  * forces must hold the forces of the incoming positions.  Asynchronous and
- * graph-capturable like pimdb_exchange_forces.  energy may be NULL. */
+ * graph-capturable like pimdb_exchange_forces.  energy may be NULL.
+ * PIMDB_EINVAL for null pointers or a non-finite dt. */
 int pimdb_md_step(pimdb_t h, double *pos, double *vel, double *forces, double *energy, double dt);
 
 /* Forces and energies of distinguishable particles (each particle its own
- * closed ring; no exchange) with the same layout and trap/box settings; the
- * reference cost the paper compares bosonic PIMD with. */
+ * closed ring; no exchange), the ordinary PIMD that the paper's "Benchmarks &
+ * Applications" compares bosonic PIMD with; same layout and trap/box
+ * settings. */
 int pimdb_distinguishable_forces(pimdb_t h, const double *pos, double *forces, double *energy);
 
+/* ------------------------------------------------------------ exports */
+
 /* Synchronous export of intermediates for system s (see PIMDB_DEBUG_*) into
- * device memory dst, recomputed from pos.  For tests and analysis; allocates
- * nothing but synchronises the stream. */
+ * device memory dst, recomputed from pos: cycle energies E^[u,v] (Theory,
+ * "Reducing the potential"), V^[1,v] (Background recurrence), V^[u,N] and
+ * Pr[l -> l'] (Theory, "Connection probabilities"; Methods, "Expressions for
+ * connection probabilities").  For tests and analysis; allocates nothing
+ * but synchronises the stream.  PIMDB_EINVAL for s out of range or an
+ * unknown `what`. */
 int pimdb_debug_get(pimdb_t h, const double *pos, int32_t s, int what, double *dst);
 
-/* Endpoint springs s(v,u) = k |r_v^P - r_u^1|^2 of system s, packed lower
- * triangle row by row (row v = 1..N holds u = 1..v; entry (v,u) at index
- * v(v-1)/2 + u-1), FP64 (as_float = 0) or FP32 (as_float = 1, compensated),
- * into device memory dst.  Asynchronous.  This is the pairwise part the
- * exchange kernels evaluate in registers without storing it. */
+/* Endpoint springs s(v,u) = k |r_v^P - r_u^1|^2 of system s (the closing
+ * spring of the cycle energy E^[u,v], Theory, "Reducing the potential"),
+ * packed lower triangle row by row (row v = 1..N holds u = 1..v; entry (v,u)
+ * at index v(v-1)/2 + u-1), FP64 (as_float = 0) or FP32 (as_float = 1,
+ * compensated), into device memory dst.  Asynchronous.  This is the
+ * pairwise part the exchange kernels evaluate in registers without storing
+ * it. */
 int pimdb_endpoint_springs(pimdb_t h, const double *pos, int32_t s, int as_float, void *dst);
 
-/* Synchronise the stream, read and clear the device status word.  *flags
- * (may be NULL) receives the PIMDB_STATUS_* bits.  Returns PIMDB_ENONFINITE
- * if any bit was set, PIMDB_OK otherwise. */
+/* Synchronise the stream, read and clear the device status word of the
+ * workspace the last evaluation used.  *flags (may be NULL) receives the
+ * PIMDB_STATUS_* bits.  Returns PIMDB_ENONFINITE if any bit was set,
+ * PIMDB_OK otherwise, PIMDB_EWORKSPACE if no workspace was ever used. */
 int pimdb_status(pimdb_t h, int32_t *flags);
 
 /* Static text for a return code. */

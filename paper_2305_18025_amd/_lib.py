@@ -22,10 +22,12 @@ PIMDB_ERANGE = -6
 
 PIMDB_FP64 = 0
 PIMDB_MIXED = 1
+PIMDB_FP64_DIRECT = 2
 
 STATUS_NONFINITE_INPUT = 1
 STATUS_NONFINITE_OUTPUT = 2
 STATUS_RANGE = 4
+STATUS_PRECISION = 8
 
 DEBUG_PROBABILITIES = 1
 DEBUG_CYCLE_ENERGIES = 2
@@ -43,7 +45,7 @@ _handle = ctypes.c_void_p
 
 # name -> (restype, argtypes); kept in the order of include/pimdb.h
 SIGNATURES = {
-    "pimdb_create": (_c_int, [ctypes.POINTER(_handle), _c_int]),
+    "pimdb_create": (_c_int, [ctypes.POINTER(_handle), _c_int, _vp]),
     "pimdb_destroy": (_c_int, [_handle]),
     "pimdb_set_stream": (_c_int, [_handle, _vp]),
     "pimdb_set_system": (_c_int, [_handle, _c_i64, _c_i32, _c_dbl, _c_dbl, _c_dbl]),
@@ -59,6 +61,7 @@ SIGNATURES = {
     "pimdb_bind_workspace": (_c_int, [_handle, _vp, _c_sz]),
     "pimdb_exchange_energy": (_c_int, [_handle, _vp, _vp]),
     "pimdb_exchange_forces": (_c_int, [_handle, _vp, _vp, _vp]),
+    "pimdb_exchange_forces_batched": (_c_int, [_handle, _vp, _vp, _vp, _vp]),
     "pimdb_exchange_forces_static": (_c_int, [_handle, _vp, _vp, _vp]),
     "pimdb_state_bytes": (_c_sz, [_handle]),
     "pimdb_exchange_energy_save": (_c_int, [_handle, _vp, _vp, _vp]),

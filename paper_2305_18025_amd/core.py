@@ -49,15 +49,18 @@ class BosonicExchange:
         else:
             self.omega_p = _as_list(omega_p, S, "omega_p", float)
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self._captured = False
+        self._old_workspaces = []
         h = ctypes.c_void_p()
-        check(self.lib.pimdb_create(ctypes.byref(h), self.device.index or 0))
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        check(self.lib.pimdb_create(ctypes.byref(h), self.device.index or 0, ctypes.c_void_p(st)))
         self._h = h
         self.box = float(box)
         self.trap = float(trap)
         self.precision = precision
         check(self.lib.pimdb_set_box(h, self.box), h)
         check(self.lib.pimdb_set_trap(h, self.trap), h)
-        mode = {"fp64": _lib.PIMDB_FP64, "mixed": _lib.PIMDB_MIXED}[precision]
+        mode = {"fp64": _lib.PIMDB_FP64, "mixed": _lib.PIMDB_MIXED, "fp64_direct": _lib.PIMDB_FP64_DIRECT}[precision]
         check(self.lib.pimdb_set_precision(h, mode), h)
         arr = lambda t, v: (t * S)(*v)
         check(self.lib.pimdb_set_batch(h, S, arr(ctypes.c_int64, self.N), arr(ctypes.c_int32, self.P),
@@ -70,6 +73,9 @@ class BosonicExchange:
     # ------------------------------------------------------------ plumbing
     def _bind(self):
         h = self._h
+        if getattr(self, "_captured", False) and getattr(self, "workspace", None) is not None:
+            # a captured graph still uses the old workspace: keep it alive
+            self._old_workspaces.append(self.workspace)
         nbytes = int(self.lib.pimdb_workspace_bytes(h))
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
@@ -80,6 +86,8 @@ class BosonicExchange:
         self.total = int(self.lib.pimdb_total_elements(h))
 
     def set_tuning(self, threads: int, per_thread: int):
+        """Change the launch shape.  Graphs captured earlier stay valid: the
+        library keeps their tables and this object their workspace."""
         check(self.lib.pimdb_set_tuning(self._h, int(threads), int(per_thread)), self._h)
         self._bind()
 
@@ -90,6 +98,8 @@ class BosonicExchange:
         return t.value, p.value
 
     def _stream(self):
+        if torch.cuda.is_current_stream_capturing():
+            self._captured = True
         st = torch.cuda.current_stream(self.device).cuda_stream
         check(self.lib.pimdb_set_stream(self._h, ctypes.c_void_p(st)), self._h)
 
@@ -153,6 +163,22 @@ class BosonicExchange:
         e_ptr = self._ptr(energy, self.S, "energy") if energy is not None else None
         check(self.lib.pimdb_exchange_forces(self._h, self._ptr(pos, self.total, "pos"),
                                              self._ptr(out, self.total, "forces"), e_ptr), self._h)
+        return out, energy
+
+    def forces_batched(self, pos, offsets, out, energy):
+        """Forces and energies of systems packed at caller-chosen element
+        offsets: `offsets` is a device int64 tensor of S offsets into `pos`
+        and `out` (system s occupies 3 P_s N_s elements from offsets[s])."""
+        if offsets.dtype != torch.int64 or offsets.device != self.device or offsets.numel() != self.S:
+            raise TypeError("offsets must be an int64 tensor of %d entries on %s" % (self.S, self.device))
+        for t, name in ((pos, "pos"), (out, "forces")):
+            if t.dtype != torch.float64 or t.device != self.device or not t.is_contiguous():
+                raise TypeError("%s must be a contiguous float64 tensor on %s" % (name, self.device))
+        self._stream()
+        check(self.lib.pimdb_exchange_forces_batched(self._h, ctypes.c_void_p(pos.data_ptr()),
+                                                     ctypes.c_void_p(offsets.contiguous().data_ptr()),
+                                                     ctypes.c_void_p(out.data_ptr()),
+                                                     self._ptr(energy, self.S, "energy")), self._h)
         return out, energy
 
     def forces_static(self, pos, out=None, energy=None, want_energy=True):
@@ -226,6 +252,7 @@ class BosonicExchange:
         return out
 
     def status(self) -> int:
+        self._stream()
         flags = ctypes.c_int32(0)
         rc = self.lib.pimdb_status(self._h, ctypes.byref(flags))
         if rc not in (_lib.PIMDB_OK, _lib.PIMDB_ENONFINITE):

@@ -39,6 +39,10 @@ struct pimdb_ctx {
     int n_fb = 0, n_f = 0, n_b = 0, n_s = 0;
     EChunk *d_echunks = nullptr;
     int n_echunks = 0;
+    // tables replaced after a call was captured into a graph: the graph
+    // still reads them, so they are freed only by pimdb_destroy
+    bool captured = false;
+    std::vector<void *> retired;
     // settings
     double box = 0.0, trap_w = 0.0;
     int precision = PIMDB_FP64;
@@ -150,10 +154,20 @@ void auto_tuning(int64_t Nmax, int S, int &threads, int &per) {
     }
 }
 
-void free_tables(pimdb_t h) {
-    if (h->d_desc) (void)hipFree(h->d_desc);
-    if (h->d_items) (void)hipFree(h->d_items);
-    if (h->d_echunks) (void)hipFree(h->d_echunks);
+// Release the current tables: freed at once, or kept until pimdb_destroy
+// if a graph may hold them.
+void free_tables(pimdb_t h, bool all = false) {
+    for (void *p : {(void *)h->d_desc, (void *)h->d_items, (void *)h->d_echunks}) {
+        if (!p) continue;
+        if (h->captured && !all)
+            h->retired.push_back(p);
+        else
+            (void)hipFree(p);
+    }
+    if (all) {
+        for (void *p : h->retired) (void)hipFree(p);
+        h->retired.clear();
+    }
     h->d_desc = nullptr;
     h->d_items = nullptr;
     h->d_echunks = nullptr;
@@ -276,6 +290,7 @@ LaunchArgs base_args(pimdb_t h, char *ws) {
     a.inv_box = h->box > 0 ? 1.0 / h->box : 0.0;
     a.trap_w2 = h->trap_w * h->trap_w;
     a.mixed = h->precision == PIMDB_MIXED;
+    a.direct = h->precision == PIMDB_FP64_DIRECT;
     return a;
 }
 
@@ -289,6 +304,8 @@ int run(pimdb_t h, LaunchArgs &a, const Item *items, int n) {
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, PIMDB_EDEVICE, "cannot select device");
     h->status_ws = (char *)a.flags;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(h->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) h->captured = true;
     a.items = items;
     hipError_t e = launch_exchange(a, n, h->threads, h->per_thread, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "exchange launch");
@@ -329,7 +346,7 @@ int set_batch_impl(pimdb_t h, int32_t S, const int64_t *N, const int32_t *P, con
 
 extern "C" {
 
-int pimdb_create(pimdb_t *out, int device) {
+int pimdb_create(pimdb_t *out, int device, void *stream) {
     if (!out) return PIMDB_EINVAL;
     *out = nullptr;
     int count = 0;
@@ -338,6 +355,7 @@ int pimdb_create(pimdb_t *out, int device) {
     pimdb_t h = new (std::nothrow) pimdb_ctx();
     if (!h) return PIMDB_EDEVICE;
     h->device = device;
+    h->stream = (hipStream_t)stream;
     {
         DeviceGuard g(device);
         if (!g.ok) {
@@ -355,7 +373,7 @@ int pimdb_destroy(pimdb_t h) {
     {
         DeviceGuard g(h->device);
         (void)hipStreamSynchronize(h->stream);
-        free_tables(h);
+        free_tables(h, true);
     }
     delete h;
     return PIMDB_OK;
@@ -392,7 +410,8 @@ int pimdb_set_trap(pimdb_t h, double w) {
 
 int pimdb_set_precision(pimdb_t h, int mode) {
     if (!h) return PIMDB_EINVAL;
-    if (mode != PIMDB_FP64 && mode != PIMDB_MIXED) return fail(h, PIMDB_EINVAL, "unknown precision mode");
+    if (mode != PIMDB_FP64 && mode != PIMDB_MIXED && mode != PIMDB_FP64_DIRECT)
+        return fail(h, PIMDB_EINVAL, "unknown precision mode");
     h->precision = mode;
     return PIMDB_OK;
 }
@@ -477,6 +496,21 @@ int pimdb_exchange_forces(pimdb_t h, const double *pos, double *forces, double *
     a.out = forces;
     a.energy = energy;
     a.mode = M_FWD | M_BWD | M_WSUM | M_FORCES | (energy ? M_ENERGY : 0);
+    return run(h, a, items_fb(h), h->n_fb);
+}
+
+int pimdb_exchange_forces_batched(pimdb_t h, const double *pos_packed, const int64_t *offsets_dev,
+                                  double *forces_packed, double *energies) {
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (!pos_packed || !offsets_dev || !forces_packed || !energies) return fail(h, PIMDB_EINVAL, "null pointer");
+    if (pos_packed == forces_packed) return fail(h, PIMDB_EINVAL, "positions and forces alias");
+    LaunchArgs a = base_args(h, h->ws);
+    a.pos = pos_packed;
+    a.out = forces_packed;
+    a.energy = energies;
+    a.offs = offsets_dev;
+    a.mode = M_FWD | M_BWD | M_WSUM | M_FORCES | M_ENERGY;
     return run(h, a, items_fb(h), h->n_fb);
 }
 

@@ -891,13 +891,58 @@ __device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDes
 
 // Dispatch on the number of rows the system needs, JJ = ceil(N / T) <= J,
 // so that no thread carries rows past the end of a smaller system.
+// The one-row kernels round term exponents with the row constant (MAG)
+// when the system is narrow enough for the low word not to wrap (wrap_ok),
+// else with the saturating sequence.
 template <int JJ, int J, bool FWD, bool BOX, bool MIXED, bool WSUM>
-__device__ __forceinline__ void rec_dispatch(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c, int jj) {
+__device__ __forceinline__ void rec_dispatch(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c, int jj,
+                                             bool wrap_ok) {
     if constexpr (JJ <= J) {
-        if (jj == JJ)
-            recursion_rows<FWD, JJ, BOX, MIXED, WSUM, (J <= 2), (J == 1)>(a, sd, c);
-        else
-            rec_dispatch<JJ + 1, J, FWD, BOX, MIXED, WSUM>(a, sd, c, jj);
+        if (jj == JJ) {
+            if constexpr (J == 1) {
+                if (wrap_ok)
+                    recursion_rows<FWD, JJ, BOX, MIXED, WSUM, true, true>(a, sd, c);
+                else
+                    recursion_rows<FWD, JJ, BOX, MIXED, WSUM, true, false>(a, sd, c);
+            } else {
+                recursion_rows<FWD, JJ, BOX, MIXED, WSUM, (J <= 2), false>(a, sd, c);
+            }
+        } else {
+            rec_dispatch<JJ + 1, J, FWD, BOX, MIXED, WSUM>(a, sd, c, jj, wrap_ok);
+        }
+    }
+}
+
+// Largest squared distance of a bead-1 point and of a bead-P point from the
+// origin (bead 1 of particle 0), over the whole system; every thread gets
+// the maxima.  Uses LDS slots of the partial-sum region, which the
+// recursion first writes two barriers later.
+__device__ __forceinline__ void system_extent(const RecCtx &c, double &r1, double &rP) {
+    const size_t NN = c.NN;
+    double m1 = 0.0, mP = 0.0;
+    for (int q = c.t; q < c.N; q += c.T) {
+        const double x1 = c.b1[q] - c.ox, y1 = c.b1[NN + q] - c.oy, z1 = c.b1[2 * NN + q] - c.oz;
+        const double xP = c.bP[q] - c.ox, yP = c.bP[NN + q] - c.oy, zP = c.bP[2 * NN + q] - c.oz;
+        m1 = fmax(m1, x1 * x1 + y1 * y1 + z1 * z1);
+        mP = fmax(mP, xP * xP + yP * yP + zP * zP);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        m1 = fmax(m1, __shfl_xor(m1, o));
+        mP = fmax(mP, __shfl_xor(mP, o));
+    }
+    double *slot = c.sm + L_PA;
+    const int w = c.t >> 6;
+    if ((c.t & 63) == 0) {
+        slot[2 * w] = m1;
+        slot[2 * w + 1] = mP;
+    }
+    __syncthreads();
+    r1 = 0.0;
+    rP = 0.0;
+    for (int i = 0; i < c.W; ++i) {
+        r1 = fmax(r1, slot[2 * i]);
+        rP = fmax(rP, slot[2 * i + 1]);
     }
 }
 
@@ -920,8 +965,24 @@ __device__ __forceinline__ void recursion_role(const LaunchArgs &a, const SysDes
     c.oy = c.b1[c.NN];
     c.oz = c.b1[2 * c.NN];
     c.flags = a.flags;
+    // Range checks on the system's extent D (largest bead-P to bead-1
+    // distance, at most the sum of the two radii about the origin; with
+    // the minimum image at most sqrt(3) L / 2):
+    //  - a term's exponent relative to its row's reference stays inside
+    //    +-2^31 when |kappa| D^2 <= 2^30 (term exponents are at least
+    //    kappa D^2 - 1, references at most about 2^29 + 2^28 unless the
+    //    range flag is set), which the row-constant rounding needs;
+    //  - the open FP64 dot form rounds about eps |kappa| |p - o|^2 in each
+    //    exponent: past DOT_LIM the 1e-10 accuracy is no longer assured,
+    //    which the status word reports (the direct form has no such limit).
+    double r1, rP;
+    system_extent(c, r1, rP);
+    double D = sqrt(r1) + sqrt(rP);
+    if (BOX && a.box > 0) D = fmin(D, 0.8660254037844387 * a.box);
+    const bool wrap_ok = -sd.kappa * D * D <= 1073741824.0; // 2^30
+    if (!BOX && !MIXED && c.t == 0 && -sd.kappa * fmax(r1, rP) > DOT_LIM) set_flag(a.flags, ST_PRECISION);
     const int jj = (sd.N + c.T - 1) / c.T;
-    rec_dispatch<1, J, FWD, BOX, MIXED, WSUM>(a, sd, c, jj);
+    rec_dispatch<1, J, FWD, BOX, MIXED, WSUM>(a, sd, c, jj, wrap_ok);
 }
 
 // ---------------------------------------------------------------- springs
@@ -1018,7 +1079,14 @@ template <int J, bool BOX, bool MIXED>
 __device__ __forceinline__ void exchange_body(const LaunchArgs &a) {
     extern __shared__ double sm[];
     const Item it = a.items[blockIdx.x];
-    const SysDesc sd = a.sys[it.sys];
+    SysDesc sd = a.sys[it.sys];
+    if (a.offs) { // caller-supplied packing (pimdb_exchange_forces_batched)
+        sd.off = a.offs[it.sys];
+        if (sd.off < 0) {
+            if (threadIdx.x == 0) set_flag(a.flags, ST_RANGE);
+            return;
+        }
+    }
     if (it.role == ROLE_FORWARD) {
         if (a.mode & M_WSUM)
             recursion_role<J, true, BOX, MIXED, true>(a, sd, sm);

@@ -89,10 +89,13 @@ struct LaunchArgs {
     int32_t *flags;        // status word
     double *state;         // adjoint state (M_SAVE writes it, M_ADJOINT reads it)
     const double *gscale;  // adjoint: grad of energy per system
+    const int64_t *offs;   // caller's element offset per system (device array), or null: SysDesc::off
     double box, inv_box;   // periodic box (0 = open)
     double trap_w2;        // trap omega^2 (0 = none)
     int32_t mode;
     int32_t mixed;         // 1: FP32 compensated endpoint spring lengths
+    int32_t direct;        // 1: direct-form pair lengths for open boundaries (host-side choice of variant)
+    int32_t pad;
 };
 
 // Kernel launch entry points (kernels.hip).  launch_exchange picks one of

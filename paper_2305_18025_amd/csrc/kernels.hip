@@ -125,7 +125,12 @@ template <bool BOX>
 __global__ void __launch_bounds__(FIN_T) k_finalize(LaunchArgs a) {
     __shared__ double red[FIN_T];
     const int si = blockIdx.x;
-    finalize<BOX>(a, a.sys[si], si, red);
+    SysDesc sd = a.sys[si];
+    if (a.offs) {
+        sd.off = a.offs[si];
+        if (sd.off < 0) return; // flagged by the exchange launch
+    }
+    finalize<BOX>(a, sd, si, red);
 }
 
 hipError_t launch_finalize(const LaunchArgs &a, int S, hipStream_t st) {
@@ -151,7 +156,10 @@ static hipError_t launch_j(const LaunchArgs &a, int nitems, int threads, int per
 
 hipError_t launch_exchange(const LaunchArgs &a, int nitems, int threads, int per_thread, hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
-    const bool box = a.box > 0;
+    // the periodic variants with box 0 form every pair displacement directly
+    // (the minimum image of d with L = 0 is d exactly): the open FP64 path
+    // without the dot-product expansion
+    const bool box = a.box > 0 || a.direct;
     if (box) return a.mixed ? launch_j<true, true>(a, nitems, threads, per_thread, st)
                             : launch_j<true, false>(a, nitems, threads, per_thread, st);
     return a.mixed ? launch_j<false, true>(a, nitems, threads, per_thread, st)

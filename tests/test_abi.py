@@ -41,7 +41,8 @@ def test_binding_signatures_cover_header():
 
 def test_constants_match_header():
     d = _defines()
-    for name in ["OK", "EINVAL", "ENOSYS", "EWORKSPACE", "EDEVICE", "ENONFINITE", "ERANGE", "FP64", "MIXED"]:
+    for name in ["OK", "EINVAL", "ENOSYS", "EWORKSPACE", "EDEVICE", "ENONFINITE", "ERANGE", "FP64", "MIXED",
+                 "FP64_DIRECT"]:
         assert getattr(_lib, "PIMDB_" + name) == d["PIMDB_" + name]
     assert _lib.MAX_N == d["PIMDB_MAX_N"]
     assert _lib.MAX_BATCH == d["PIMDB_MAX_BATCH"]
@@ -49,6 +50,7 @@ def test_constants_match_header():
     assert _lib.DEBUG_PROBABILITIES == d["PIMDB_DEBUG_PROBABILITIES"]
     assert _lib.DEBUG_BACKWARD == d["PIMDB_DEBUG_BACKWARD"]
     assert _lib.STATUS_RANGE == d["PIMDB_STATUS_RANGE"]
+    assert _lib.STATUS_PRECISION == d["PIMDB_STATUS_PRECISION"]
 
 
 def test_strerror_texts():
@@ -67,7 +69,7 @@ def test_null_handle_is_rejected():
     assert lib.pimdb_workspace_bytes(None) == 0
     assert lib.pimdb_system_offset(None, 0) == -1
     assert lib.pimdb_destroy(None) == _lib.PIMDB_OK
-    assert lib.pimdb_create(None, 0) == _lib.PIMDB_EINVAL
+    assert lib.pimdb_create(None, 0, None) == _lib.PIMDB_EINVAL
 
 
 def test_create_without_gpu_reports_device_error():
@@ -76,5 +78,5 @@ def test_create_without_gpu_reports_device_error():
         pytest.skip("a GPU is visible")
     lib = _lib.load()
     h = ctypes.c_void_p(123)
-    assert lib.pimdb_create(ctypes.byref(h), 0) == _lib.PIMDB_EDEVICE
+    assert lib.pimdb_create(ctypes.byref(h), 0, None) == _lib.PIMDB_EDEVICE
     assert h.value is None

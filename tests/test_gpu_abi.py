@@ -1,0 +1,135 @@
+"""GPU: entry points of the C ABI called through ctypes -- the batched
+evaluation with caller-supplied device offsets, the stream given at
+creation, and graphs that survive a change of launch shape."""
+import concurrent.futures as cf
+import ctypes
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2305_18025_amd import BosonicExchange, _lib, inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+OK = _lib.PIMDB_OK
+
+
+def _vp(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _oracle_f80(s):
+    return oracle.alg1(s.R, s.beta, s.m, s.omegaP, L=s.box, precision="f80", extras=False)
+
+
+def _threads():
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        return 4
+
+
+def test_batched_entry_with_caller_offsets_64_systems():
+    """pimdb_exchange_forces_batched on the 64-system batch packed by the
+    caller in reverse order with a gap of 13 elements before every system
+    (so no offset equals the library's own packing), stream given at
+    pimdb_create; every system against the long-double oracle at 1e-10 and
+    the gaps left untouched."""
+    systems = inputs.config_batch()
+    S = len(systems)
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    stream = torch.cuda.Stream()
+    assert lib.pimdb_create(ctypes.byref(h), 0, ctypes.c_void_p(stream.cuda_stream)) == OK
+    try:
+        arr = lambda typ, v: (typ * S)(*v)
+        assert lib.pimdb_set_batch(h, S, arr(ctypes.c_int64, [s.N for s in systems]),
+                                   arr(ctypes.c_int32, [s.P for s in systems]),
+                                   arr(ctypes.c_double, [s.beta for s in systems]),
+                                   arr(ctypes.c_double, [s.m for s in systems]),
+                                   arr(ctypes.c_double, [s.omegaP for s in systems])) == OK
+        offs = [0] * S
+        cur = 0
+        for i in reversed(range(S)):
+            cur += 13
+            offs[i] = cur
+            cur += systems[i].R.size
+        total = cur + 7
+        host = np.full(total, -1.0)
+        for i, s in enumerate(systems):
+            host[offs[i]:offs[i] + s.R.size] = inputs.to_soa(s.R).ravel()
+        with torch.cuda.stream(stream):
+            pos = torch.from_numpy(host).cuda()
+            F = torch.full((total,), 7.0, dtype=torch.float64, device="cuda")
+            E = torch.empty(S, dtype=torch.float64, device="cuda")
+            doff = torch.tensor(offs, dtype=torch.int64, device="cuda")
+            nbytes = int(lib.pimdb_workspace_bytes(h))
+            ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        stream.synchronize()
+        aligned = (ws.data_ptr() + 255) // 256 * 256
+        assert lib.pimdb_bind_workspace(h, ctypes.c_void_p(aligned), nbytes) == OK
+        assert lib.pimdb_exchange_forces_batched(h, _vp(pos), _vp(doff), _vp(F), _vp(E)) == OK
+        flags = ctypes.c_int32(-1)
+        assert lib.pimdb_status(h, ctypes.byref(flags)) == OK and flags.value == 0
+        Fh = F.cpu().numpy()
+        Eh = E.cpu().numpy()
+        mask = np.ones(total, bool)
+        for i, s in enumerate(systems):
+            mask[offs[i]:offs[i] + s.R.size] = False
+        assert (Fh[mask] == 7.0).all(), "elements outside the systems were written"
+        with cf.ThreadPoolExecutor(_threads()) as ex:
+            refs = list(ex.map(_oracle_f80, systems))
+        worst = (0.0, 0.0)
+        for i, (s, o) in enumerate(zip(systems, refs)):
+            Fi = inputs.from_soa(Fh[offs[i]:offs[i] + s.R.size].reshape(s.P, 3, s.N))
+            ee = abs(Eh[i] - o["V"]) / abs(o["V"])
+            fe = float(np.abs(Fi - o["F"]).max() / np.abs(o["F"]).max())
+            worst = (max(worst[0], ee), max(worst[1], fe))
+            assert ee <= TOL64 and fe <= TOL64, (i, s.name, ee, fe)
+        print("caller-packed 64 systems: worst energy %.2e forces %.2e" % worst)
+        # a negative offset skips its system and raises the range bit
+        doff[5] = -1
+        E.fill_(123.0)
+        torch.cuda.synchronize()  # the library runs on its own stream
+        assert lib.pimdb_exchange_forces_batched(h, _vp(pos), _vp(doff), _vp(F), _vp(E)) == OK
+        assert lib.pimdb_status(h, ctypes.byref(flags)) == _lib.PIMDB_ENONFINITE and flags.value == _lib.STATUS_RANGE
+        assert float(E[5]) == 123.0 and abs(float(E[4]) - Eh[4]) <= 1e-15 * abs(Eh[4])
+        assert lib.pimdb_exchange_forces_batched(h, None, _vp(doff), _vp(F), _vp(E)) == _lib.PIMDB_EINVAL
+    finally:
+        lib.pimdb_destroy(h)
+
+
+def test_graph_survives_retuning():
+    """A graph captured with one launch shape keeps replaying correctly after
+    the engine is re-tuned (the library keeps the tables the graph reads,
+    the binding keeps its workspace); eager calls use the new shape."""
+    s = inputs.config_plain()
+    eng = BosonicExchange(s.N, s.P, s.beta, s.m, s.omegaP)
+    pos = eng.pack(s.R)
+    F0, E0 = eng.forces(pos)
+    F0, E0 = F0.clone(), E0.clone()
+    F = eng.empty()
+    E = torch.empty(1, dtype=torch.float64, device=pos.device)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            eng.forces(pos, out=F, energy=E)
+    torch.cuda.current_stream().wait_stream(side)
+    old = eng.tuning
+    eng.set_tuning(64, 8)
+    assert eng.tuning != old
+    for _ in range(3):
+        F.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(F, F0) and torch.equal(E, E0)
+        F1, E1 = eng.forces(pos)
+        torch.cuda.synchronize()
+        assert (F1 - F0).abs().max() <= 1e-12 * F0.abs().max()
+    assert eng.status() == 0

@@ -27,7 +27,7 @@ OK, EINVAL, ENOSYS, EWORKSPACE, ERANGE = (_lib.PIMDB_OK, _lib.PIMDB_EINVAL, _lib
 def api():
     lib = _lib.load()
     h = ctypes.c_void_p()
-    assert lib.pimdb_create(ctypes.byref(h), 0) == OK
+    assert lib.pimdb_create(ctypes.byref(h), 0, None) == OK
     yield lib, h
     torch.cuda.synchronize()
     assert lib.pimdb_destroy(h) == OK
@@ -46,10 +46,10 @@ def _set_batch(lib, h, N, P, beta, m, w):
 def test_create_rejects_bad_device():
     lib = _lib.load()
     h = ctypes.c_void_p(1)
-    assert lib.pimdb_create(ctypes.byref(h), torch.cuda.device_count()) == EINVAL
+    assert lib.pimdb_create(ctypes.byref(h), torch.cuda.device_count(), None) == EINVAL
     assert not h.value
-    assert lib.pimdb_create(ctypes.byref(h), -1) == EINVAL
-    assert lib.pimdb_create(None, 0) == EINVAL
+    assert lib.pimdb_create(ctypes.byref(h), -1, None) == EINVAL
+    assert lib.pimdb_create(None, 0, None) == EINVAL
 
 
 def test_calls_before_a_system_is_set(api):
@@ -101,7 +101,8 @@ def test_setters_and_tuning_reject(api):
         assert lib.pimdb_set_box(h, L) == EINVAL
     for wt in (-0.5, math.nan):
         assert lib.pimdb_set_trap(h, wt) == EINVAL
-    assert lib.pimdb_set_precision(h, 2) == EINVAL
+    assert lib.pimdb_set_precision(h, 3) == EINVAL
+    assert lib.pimdb_set_precision(h, -1) == EINVAL
     for threads, per in [(96, 1), (2048, 1), (64, 3), (64, 0), (1024, 4), (1024, 8)]:
         assert lib.pimdb_set_tuning(h, threads, per) == EINVAL, (threads, per)
     assert lib.pimdb_set_system(h, 1024, 4, 1.0, 1.0, 1.0) == OK

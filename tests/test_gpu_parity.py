@@ -313,6 +313,58 @@ def test_wide_clustered_system(threads, per):
     _assert_parity(eng, F, E, [s], TOL64)
 
 
+def test_wide_system_near_the_expansion_bound():
+    """Clusters over a cube of side 480 at P = 32: |kappa| max|p - o|^2 at
+    about 86% of the bound (2^23) up to which the open FP64 expansion is
+    specified to keep 1e-10; no status bit, full accuracy."""
+    s = System(_clustered(64, 8, 480.0, 32, seed=3), beta=1.0)
+    o = s.R[0, 0]
+    kap = 0.5 * s.m * s.omegaP ** 2 * s.beta / math.log(2.0)
+    r2 = max(((s.R[:, 0] - o) ** 2).sum(1).max(), ((s.R[:, -1] - o) ** 2).sum(1).max())
+    assert 0.75 * 2 ** 23 < kap * r2 < 2 ** 23
+    eng, pos = _engine([s])
+    F, E = eng.forces(pos)
+    assert eng.status() == 0
+    _assert_parity(eng, F, E, [s], TOL64)
+
+
+def _label_chain(N, P, spacing, seed):
+    """Particles along x in label order, `spacing` apart; beads N(0, 0.3^2)
+    about their particle."""
+    rng = np.random.default_rng(seed)
+    c = np.zeros((N, 3))
+    c[:, 0] = spacing * np.arange(N)
+    return c[:, None, :] + rng.normal(0.0, 0.3, (N, P, 3))
+
+
+@pytest.mark.parametrize("precision", ["fp64_direct", "mixed"])
+@pytest.mark.parametrize("threads,per", [(1024, 1), (512, 2)])
+def test_long_label_chain(precision, threads, per):
+    """1000 particles 20 units apart in label order, P = 32, beta = 1: the
+    extent D ~ 2e4 gives |kappa| D^2 ~ 9e9 binary orders, past the 2^30 up to
+    which the one-row kernels may round term exponents with the row constant
+    (its 32-bit low word would wrap), so they must take the saturating
+    sequence.  The direct FP64 form and the mixed mode keep full accuracy in
+    the one- and the two-row kernels."""
+    s = System(_label_chain(1000, 32, 20.0, seed=4), beta=1.0)
+    eng, pos = _engine([s], precision=precision, threads=threads, per_thread=per)
+    F, E = eng.forces(pos)
+    assert eng.status() == 0
+    _assert_parity(eng, F, E, [s], TOL64 if precision == "fp64_direct" else TOLMIX)
+
+
+def test_expansion_bound_sets_precision_bit():
+    """The same chain in the default FP64 mode, which expands |a - b|^2 about
+    bead 1 of particle 0: past its rounding bound the energy-only and force
+    calls report PIMDB_STATUS_PRECISION and nothing else."""
+    s = System(_label_chain(1000, 32, 20.0, seed=4), beta=1.0)
+    eng, pos = _engine([s])
+    eng.forces(pos)
+    assert eng.status() == 8
+    eng.energy(pos)
+    assert eng.status() == 8
+
+
 def test_cumulative_exponent_range_flag():
     """The same clusters over a cube of side 3000: each spring between
     consecutive labels in different clusters stays below the per-spring bound

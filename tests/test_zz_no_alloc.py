@@ -49,7 +49,7 @@ def _unpack(lib, h, F, i, s):
 def test_static_scratch_entry_matches_workspace_entry():
     lib = _lib.load()
     h = ctypes.c_void_p()
-    assert lib.pimdb_create(ctypes.byref(h), 0) == _lib.PIMDB_OK
+    assert lib.pimdb_create(ctypes.byref(h), 0, None) == _lib.PIMDB_OK
     try:
         stream = torch.cuda.current_stream().cuda_stream
         assert lib.pimdb_set_stream(h, ctypes.c_void_p(stream)) == _lib.PIMDB_OK
@@ -92,7 +92,7 @@ def test_static_scratch_entry_matches_workspace_entry():
 def test_static_scratch_rejects_oversized_batch():
     lib = _lib.load()
     h = ctypes.c_void_p()
-    assert lib.pimdb_create(ctypes.byref(h), 0) == _lib.PIMDB_OK
+    assert lib.pimdb_create(ctypes.byref(h), 0, None) == _lib.PIMDB_OK
     try:
         S = 1200  # 1200 systems of N=2048 need far more than 16 MiB of scratch
         N = (ctypes.c_int64 * S)(*([2048] * S))
