@@ -30,17 +30,18 @@ sys.path.insert(0, ROOT)
 METRIC = "exchange E+F evals/sec at N=1024,P=32 (batched vs plain, 1 GPU)"
 N_HEAD, P_HEAD, BETA = 1024, 32, 1.0
 PEAK_FP64 = 78.6e12  # MI355X FP64 vector peak: 256 CU * 4 SIMD * 16 lanes * 2 flop * 2.4 GHz
-# Algorithmic FP64 flops of one term of one recursion: spring length |d|^2
-# (3 sub + 3 mul + 2 add), exponent (mul + add), the exponential 2^x to full
-# double accuracy (range reduction 2 + the lowest-degree minimax polynomial
-# that adds no error, degree 10 = 10 FMA = 20), Boltzmann-weight
-# accumulation (mul + add) and the weighted displacement (3 mul + 3 add).
-# Two recursions of M = N(N+1)/2 terms per evaluation.
-FLOPS_PER_TERM = 8 + 2 + 22 + 2 + 6
+# Algorithmic work of one evaluation: the method's O(N^2) part is three
+# passes of M = N(N+1)/2 exponentials (the forward potentials, the backward
+# potentials and the connection probabilities), each a double-precision
+# exponential of about 16 FP64 operations (range reduction and a
+# polynomial) -- 25.2 MFLOP at N = 1024.  The fused kernels here reuse the
+# two recursions' terms for the probabilities (two passes), so this counts
+# more work than they issue.
+EXP_FLOPS = 16
 
 
 def flops_per_eval(N: int) -> float:
-    return 2.0 * (N * (N + 1) / 2) * FLOPS_PER_TERM
+    return 3.0 * (N * (N + 1) / 2) * EXP_FLOPS
 
 
 def systems(B, seed0=3, variant="gaussian"):
@@ -89,31 +90,50 @@ def time_graph(eng, pos, steps, warmup):
     return wall, e0.elapsed_time(e1) / steps, (F, E)
 
 
-def time_plain(eng, pos, calls):
-    import torch
-    F = eng.empty()
-    E = torch.empty(eng.S, dtype=torch.float64, device=eng.device)
-    for _ in range(3):
-        eng.forces(pos, out=F, energy=E)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(calls):
-        eng.forces(pos, out=F, energy=E)
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / calls
-
-
 def accuracy(eng, F, E, R_list, precision="f80", which=(0,)):
+    """Largest relative energy error and norm-wise force error
+    (max|dF| / max|F|) over the systems `which`, against the oracle, plus
+    per-component statistics of the force error."""
     import numpy as np
     import oracle
     from paper_2305_18025_amd.inputs import omega_p
     ee = fe = 0.0
+    comp = {"x": 0.0, "y": 0.0, "z": 0.0}
+    elem = []
     for s in which:
         o = oracle.alg1(R_list[s], BETA, 1.0, omega_p(P_HEAD, BETA), precision=precision, extras=False)
         Fg = eng.unpack(F, s)
+        d = np.abs(Fg - o["F"])
         ee = max(ee, abs(float(E[s]) - o["V"]) / abs(o["V"]))
-        fe = max(fe, float(np.abs(Fg - o["F"]).max() / np.abs(o["F"]).max()))
-    return ee, fe
+        fe = max(fe, float(d.max() / np.abs(o["F"]).max()))
+        for c, name in enumerate("xyz"):
+            comp[name] = max(comp[name], float(d[..., c].max() / np.abs(o["F"][..., c]).max()))
+        big = np.abs(o["F"]) > 1e-3 * np.abs(o["F"]).max()
+        elem.append(d[big] / np.abs(o["F"][big]))
+    elem = np.concatenate(elem)
+    stats = {"max_abs_err_over_max_abs_F_by_component": comp,
+             "elementwise_rel_err_median": float(np.median(elem)),
+             "elementwise_rel_err_p99": float(np.quantile(elem, 0.99)),
+             "elementwise_rel_err_max": float(elem.max()),
+             "elementwise_note": "|dF_i| / |F_i| over components with |F_i| > 1e-3 max|F|"}
+    return ee, fe, stats
+
+
+def kernel_times(eng, pos, reps):
+    """Mean durations (ms) of the exchange and finalize launches over `reps`
+    eager evaluations, from HIP events the library records on its stream."""
+    import torch
+    F = eng.empty()
+    E = torch.empty(eng.S, dtype=torch.float64, device=eng.device)
+    eng.set_timing(True)
+    ex = fi = 0.0
+    for _ in range(reps):
+        eng.forces(pos, out=F, energy=E)
+        a, b = eng.last_timing()
+        ex += a
+        fi += b
+    eng.set_timing(False)
+    return ex / reps, fi / reps
 
 
 def time_calls(fn, reps):
@@ -184,19 +204,44 @@ def extra_workloads(steps):
     return out
 
 
-def cpu_baseline(seconds, max_threads=16):
-    """The FP64 C oracle (as it stands) on the host cores: independent
-    N=1024, P=32 evaluations (energy + forces) in a thread pool for about
-    `seconds` of wall time."""
-    import concurrent.futures as cf
-    import oracle
-    from paper_2305_18025_amd.inputs import gaussian_system, omega_p
+def host_info():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     try:
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
         avail = os.cpu_count() or 1
+    return model, avail
+
+
+def cpu_baseline(seconds, max_threads=16):
+    """The FP64 C oracle (as it stands) on the host cores: single-thread
+    median latency of the plain N=256 and the headline N=1024 evaluations,
+    then independent N=1024, P=32 evaluations (energy + forces) in a thread
+    pool for about `seconds` of wall time.  The pool is capped at 16 threads,
+    the CPU share of one GPU on the measurement boxes."""
+    import concurrent.futures as cf
+    import statistics
+    import oracle
+    from paper_2305_18025_amd import inputs
+    from paper_2305_18025_amd.inputs import gaussian_system, omega_p
+    model, avail = host_info()
     cores = max(1, min(max_threads, avail))
     oracle.build(force=False)
+    single = {}
+    for name, sy in (("N256_P32_cube", inputs.config_plain()), ("N1024_P32_gaussian", inputs.config_headline())):
+        ts = []
+        for _ in range(7):
+            t0 = time.perf_counter()
+            oracle.alg1(sy.R, sy.beta, sy.m, sy.omegaP, precision="f64", extras=False)
+            ts.append(time.perf_counter() - t0)
+        single[name] = {"median_ms": statistics.median(ts) * 1e3, "evaluations": len(ts)}
     Rs = [gaussian_system(N_HEAD, P_HEAD, seed=1000 + i) for i in range(cores)]
     w = omega_p(P_HEAD, BETA)
     deadline = time.perf_counter() + seconds
@@ -214,21 +259,29 @@ def cpu_baseline(seconds, max_threads=16):
     dt = time.perf_counter() - t0
     total = sum(counts)
     return {"value": total / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
-            "sample": "%d evaluations (energy+forces, FP64 Fast PIMD-B in C, N=1024 P=32 Gaussian) "
-                      "on %d host threads in %.1f s" % (total, cores, dt)}
+            "sample": "%d evaluations (energy+forces, FP64 oracle in C, N=1024 P=32 Gaussian) "
+                      "on %d host threads in %.1f s" % (total, cores, dt),
+            "host_cpu": model, "host_cores_available": avail, "threads_used": cores,
+            "single_thread_latency": single}
+
+
+def device_sources_sha1():
+    """SHA-1 over the device sources (the exchange kernels and the others)."""
+    h = hashlib.sha1()
+    for f in ("common.h", "exchange.h", "exchange_inst.hip", "kernels.hip", "internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2305_18025_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
 
 
 def traffic_record(batch):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source and batch size."""
+    was taken on the current device sources and batch size."""
     path = os.path.join(ROOT, "profiles", "exchange_traffic.json")
-    src = os.path.join(ROOT, "paper_2305_18025_amd", "csrc", "kernels.hip")
     try:
         rec = json.load(open(path))
-        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if rec.get("kernels_hip_sha1") != sha or rec.get("batch") != batch:
+    if rec.get("device_sources_sha1") != device_sources_sha1() or rec.get("batch") != batch:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -243,7 +296,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline and plain only")
-    ap.add_argument("--autotune", action="store_true", help="time candidate launch shapes first")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's built-in launch shape instead of timing the candidates")
+    ap.add_argument("--plain-calls", type=int, default=1000)
     ap.add_argument("--profile-run", action="store_true",
                     help="only replay the headline launch (for rocprofv3 counter runs), then copy a "
                          "256 MiB buffer once as the traffic calibration kernel")
@@ -261,13 +316,15 @@ def main():
     B = args.batch
     Rb = systems(B)
 
-    # headline: batched, graph-captured, library launch shape (or autotuned)
+    # headline: batched, graph-captured, launch shape from the autotuner
     eng = make_engine(B)
     pos = eng.pack(Rb)
-    if args.autotune:
-        tuned = autotune(eng, pos, reps=2, use_cache=False)
-    else:
+    tune_log = None
+    if args.no_autotune or args.profile_run:
         tuned = eng.tuning
+    else:
+        tune_log = []
+        tuned = autotune(eng, pos, reps=3, use_cache=False, log=tune_log)
     wall, ms_launch, (F, E) = time_graph(eng, pos, args.steps, args.warmup)
     if args.profile_run:
         src = torch.empty(256 << 20, dtype=torch.uint8, device=eng.device)
@@ -280,11 +337,17 @@ def main():
     value = B * args.steps / wall
     torch.cuda.synchronize()
     status = eng.status()
+    # the dominant kernel alone: HIP events around the exchange launch
+    ms_exchange, ms_finalize = kernel_times(eng, pos, max(10, args.steps))
 
-    # plain: one system per call, no graph, default (latency) launch shape
+    # plain: one system per call, no graph, library launch shape; HIP events
+    # on the library's stream (torch's current stream) over the calls
     eng1 = make_engine(1)
     pos1 = eng1.pack(Rb[0])
-    sec_plain = time_plain(eng1, pos1, max(100, args.steps))
+    F1 = eng1.empty()
+    E1 = torch.empty(1, dtype=torch.float64, device=eng1.device)
+    ms_plain = time_calls(lambda: eng1.forces(pos1, out=F1, energy=E1), args.plain_calls)
+    ms_plain_ex, ms_plain_fin = kernel_times(eng1, pos1, 20)
 
     out = {
         "metric": METRIC,
@@ -306,26 +369,35 @@ def main():
             "N": N_HEAD, "P": P_HEAD, "batch": B, "precision": "fp64", "graph": True,
             "launch_shape": {"threads": tuned[0], "per_thread": tuned[1]},
         },
-        "plain": {"value": 1.0 / sec_plain, "unit": "evals/s", "ms_per_eval": sec_plain * 1e3,
-                  "description": "one system per call, no graph"},
-        "batched_over_plain": value * sec_plain,
+        "plain": {"value": 1e3 / ms_plain, "unit": "evals/s", "ms_per_eval": ms_plain, "calls": args.plain_calls,
+                  "exchange_kernel_ms": ms_plain_ex, "finalize_kernel_ms": ms_plain_fin,
+                  "ns_per_recursion_step": ms_plain * 1e6 / N_HEAD,
+                  "description": "one system per call, no graph, HIP events over the calls"},
+        "batched_over_plain": value * ms_plain * 1e-3,
         "device_status": status,
     }
+    if tune_log is not None:
+        out["autotune"] = tune_log
     flops = B * flops_per_eval(N_HEAD)
-    achieved = flops / (ms_launch * 1e-3)
+    achieved = flops / (ms_exchange * 1e-3)
     out["roofline"] = {
         "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
         "frac": achieved / PEAK_FP64, "traffic": traffic_record(B),
-        "kernel": "pimdb::k_exchange%s<%d, false, false> (fused springs + recursions + forces)"
+        "kernel": "pimdb::k_exchange%s<%d, false, false> (fused springs + recursions)"
                   % ("_wide" if tuned[1] >= 4 else "", tuned[1]),
-        "ms_per_launch_hip_events": ms_launch,
+        "ms_per_launch_hip_events": ms_exchange,
+        "finalize_ms_hip_events": ms_finalize,
+        "graph_replay_ms": ms_launch,
         "flops_per_launch": flops,
-        "flops_per_term": FLOPS_PER_TERM,
+        "flops_per_eval": flops_per_eval(N_HEAD),
+        "flop_model": "3 passes of N(N+1)/2 FP64 exponentials at %d flops each" % EXP_FLOPS,
+        "device_sources_sha1": device_sources_sha1(),
     }
 
     if not args.quick:
-        ee, fe = accuracy(eng, F, E, Rb, "f80", which=(0, B - 1))
-        out["accuracy_vs_oracle_f80"] = {"energy_rel": ee, "forces_rel_max": fe, "tolerance": 1e-10}
+        ee, fe, st = accuracy(eng, F, E, Rb, "f80", which=(0, B - 1))
+        out["accuracy_vs_oracle_f80"] = {"energy_rel": ee, "forces_rel_max": fe, "tolerance": 1e-10,
+                                         "forces_per_component": st}
         sweep = {}
         for b in [int(x) for x in args.sweep.split(",") if x]:
             e_b = make_engine(b)
@@ -338,7 +410,7 @@ def main():
         em = make_engine(B, precision="mixed", tuning=tuned[:2])
         pm = em.pack(Rb)
         w_m, ms_m, (Fm, Em) = time_graph(em, pm, max(5, args.steps // 2), 2)
-        eem, fem = accuracy(em, Fm, Em, Rb, "f80", which=(0,))
+        eem, fem, _ = accuracy(em, Fm, Em, Rb, "f80", which=(0,))
         out["mixed"] = {"evals_per_s": B * max(5, args.steps // 2) / w_m, "energy_rel": eem,
                         "forces_rel_max": fem, "tolerance": 1e-5,
                         "description": "FP32 compensated endpoint-spring lengths, FP64 elsewhere"}
@@ -358,7 +430,6 @@ def main():
                                   "description": "ring-polymer springs without exchange, same batch",
                                   "springs_TB_per_s": spring_bytes / sec_d / 1e12,
                                   "springs_frac_of_8TBs": spring_bytes / sec_d / 8e12}
-        out["plain"]["ns_per_recursion_step"] = sec_plain * 1e9 / N_HEAD
         out.update(extra_workloads(args.steps))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

@@ -91,6 +91,8 @@ extern "C" {
                                            whose binary exponent passed +-2^29 (the chain's
                                            cumulative spring exponents, e.g. particles with
                                            consecutive labels thousands of length units apart) */
+#define PIMDB_STATUS_TIMEOUT 16         /* a workgroup of a split recursion waited more than 2 s
+                                           for another (results invalid) */
 #define PIMDB_STATUS_PRECISION 8        /* PIMDB_FP64 on an open system whose extent passes the
                                            expansion's rounding bound: beta*k*log2(e)*max|r - r_0^1|^2
                                            above 2^23 (about 600 length units at beta k = 16).
@@ -176,6 +178,36 @@ int pimdb_set_precision(pimdb_t h, int mode);
  * pimdb_set_batch; graphs captured before keep working (the replaced tables
  * stay allocated until pimdb_destroy) as long as their workspace does. */
 int pimdb_set_tuning(pimdb_t h, int threads, int per_thread);
+
+/* Timing mode (enable = 1; 0 turns it off): every later evaluation that is
+ * not being captured into a graph records HIP events on the handle's stream
+ * before and after the exchange launch and after the finalize launch.
+ * Creates the events on first use.  For measurement, not for graphs. */
+int pimdb_set_timing(pimdb_t h, int enable);
+
+/* Durations in ms of the two launches of the last timed evaluation
+ * (waits for it): the fused exchange launch (springs and recursions) and
+ * the finalize launch (exterior forces and energies).  PIMDB_ENOSYS if no
+ * evaluation has been timed since timing was enabled. */
+int pimdb_last_timing(pimdb_t h, float *exchange_ms, float *finalize_ms);
+
+/* Split recursions: spread each system's forward and backward recursion
+ * over 1 + nhelp workgroups on different CUs, so that small batches use the
+ * device (the serial chain of steps stays in one workgroup; helper
+ * workgroups add the terms of published blocks to the accumulators they own
+ * and deliver them to the chain; the accumulators follow the terms of the
+ * recurrences of Background and Theory, "Connection probabilities").
+ * blocks_per_helper: -1 automatic (default: split when the batch has fewer
+ * recursion workgroups than a quarter of the CUs), 0 never, g >= 1 at most g
+ * blocks of 64 accumulators per helper.  Systems of N <= 128 are never split.
+ * Results equal those of the whole recursions up to rounding.  PIMDB_EINVAL
+ * if the plan would not fit the workgroups the device holds at once.  With a
+ * system set, rebuilds the tables and unbinds the workspace. */
+int pimdb_set_split(pimdb_t h, int blocks_per_helper);
+
+/* Blocks per helper of the current tables (0: no system split) and the
+ * number of helper workgroups a forces call launches. */
+int pimdb_get_split(pimdb_t h, int *blocks_per_helper, int *helpers);
 
 /* Current launch shape (after the automatic choice). */
 int pimdb_get_tuning(pimdb_t h, int *threads, int *per_thread);

@@ -28,6 +28,7 @@ STATUS_NONFINITE_INPUT = 1
 STATUS_NONFINITE_OUTPUT = 2
 STATUS_RANGE = 4
 STATUS_PRECISION = 8
+STATUS_TIMEOUT = 16
 
 DEBUG_PROBABILITIES = 1
 DEBUG_CYCLE_ENERGIES = 2
@@ -54,6 +55,10 @@ SIGNATURES = {
     "pimdb_set_trap": (_c_int, [_handle, _c_dbl]),
     "pimdb_set_precision": (_c_int, [_handle, _c_int]),
     "pimdb_set_tuning": (_c_int, [_handle, _c_int, _c_int]),
+    "pimdb_set_timing": (_c_int, [_handle, _c_int]),
+    "pimdb_last_timing": (_c_int, [_handle, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+    "pimdb_set_split": (_c_int, [_handle, _c_int]),
+    "pimdb_get_split": (_c_int, [_handle, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]),
     "pimdb_get_tuning": (_c_int, [_handle, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]),
     "pimdb_system_offset": (_c_i64, [_handle, _c_i32]),
     "pimdb_total_elements": (_c_i64, [_handle]),

@@ -34,7 +34,7 @@ class BosonicExchange:
     """
 
     def __init__(self, N, P, beta, m=1.0, omega_p=None, *, device=0, box=0.0, trap=0.0,
-                 precision="fp64", threads=0, per_thread=0):
+                 precision="fp64", threads=0, per_thread=0, split=-1):
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("BosonicExchange needs a GPU")
@@ -68,6 +68,8 @@ class BosonicExchange:
                                        arr(ctypes.c_double, self.omega_p)), h)
         if threads or per_thread:
             check(self.lib.pimdb_set_tuning(h, int(threads), int(per_thread)), h)
+        if split != -1:
+            check(self.lib.pimdb_set_split(h, int(split)), h)
         self._bind()
 
     # ------------------------------------------------------------ plumbing
@@ -90,6 +92,32 @@ class BosonicExchange:
         library keeps their tables and this object their workspace."""
         check(self.lib.pimdb_set_tuning(self._h, int(threads), int(per_thread)), self._h)
         self._bind()
+
+    def set_timing(self, enable: bool = True):
+        """Record HIP events around the exchange and finalize launches of
+        every later eager evaluation (see last_timing)."""
+        check(self.lib.pimdb_set_timing(self._h, 1 if enable else 0), self._h)
+
+    def last_timing(self):
+        """(exchange launch ms, finalize launch ms) of the last timed eager
+        evaluation, from HIP events on the library's stream."""
+        a, b = ctypes.c_float(), ctypes.c_float()
+        check(self.lib.pimdb_last_timing(self._h, ctypes.byref(a), ctypes.byref(b)), self._h)
+        return a.value, b.value
+
+    def set_split(self, blocks_per_helper: int):
+        """Split recursions: -1 automatic, 0 never, g >= 1 at most g blocks of
+        64 accumulators per helper workgroup (see include/pimdb.h)."""
+        check(self.lib.pimdb_set_split(self._h, int(blocks_per_helper)), self._h)
+        self._bind()
+
+    @property
+    def split(self):
+        """(blocks per helper of the current plan, 0 if unsplit; helper
+        workgroups per forces call)."""
+        g, n = ctypes.c_int(), ctypes.c_int()
+        check(self.lib.pimdb_get_split(self._h, ctypes.byref(g), ctypes.byref(n)), self._h)
+        return g.value, n.value
 
     @property
     def tuning(self):

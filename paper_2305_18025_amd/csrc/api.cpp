@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -43,11 +44,22 @@ struct pimdb_ctx {
     // still reads them, so they are freed only by pimdb_destroy
     bool captured = false;
     std::vector<void *> retired;
+    // optional HIP events around the two launches of an eager evaluation
+    bool timing = false;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    bool ev_recorded = false;
     // settings
     double box = 0.0, trap_w = 0.0;
     int precision = PIMDB_FP64;
     int user_threads = 0, user_per = 0;
     int threads = 256, per_thread = 4;
+    // split recursions: user setting (-1 automatic, 0 off, g >= 1 blocks per
+    // helper) and what the current tables use
+    int user_split = -1;
+    int split_g = 0;       // 0: no system split
+    int helpers_total = 0; // helper workgroups of a forces launch
+    int cus = 0;           // compute units of the device
+    uint64_t wait_ticks = 200000000ull; // split waits give up after 2 s (100 MHz clock)
     // workspace
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -79,7 +91,7 @@ void scratch_setup(int dev) {
     if (g_scratch[dev] || g_scratch_err[dev] != hipSuccess) return;
     void *p = nullptr;
     hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
-    if (e == hipSuccess) e = launch_clear((int32_t *)p, WS_HEADER_BYTES / 4, nullptr);
+    if (e == hipSuccess) e = launch_clear((int32_t *)p, PIMDB_STATIC_SCRATCH_BYTES / 4, nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
         g_scratch_err[dev] = e;
@@ -154,6 +166,69 @@ void auto_tuning(int64_t Nmax, int S, int &threads, int &per) {
     }
 }
 
+// Split recursions (exchange.h): a system of nblk = ceil(N / 64) >= 3
+// blocks gets nhelp = ceil((nblk - 2) / g) helper workgroups per direction,
+// each owning at most g of the blocks 2 .. nblk-1 (forward; backward
+// mirrored) on its W - 1 = 7 row waves (rows per thread = ceil(owned / 7)
+// <= 2).  Systems of one or two blocks stay whole.  The launch uses the
+// 512-thread split kernel and must fit the workgroups the device holds at
+// once, since the chain and helpers of a system wait on each other.
+constexpr int SPLIT_T = 512;
+constexpr int SPLIT_ROWS = SPLIT_T / 64 - 1;
+
+struct SplitPlan {
+    int per = 1;
+    int helpers = 0; // per forces launch (both directions)
+    int recursion_wgs = 0;
+    std::vector<int> nhelp;
+};
+
+int helpers_for(int64_t N, int g) {
+    const int nblk = (int)((N + 63) / 64);
+    if (nblk < 3 || g < 1) return 0;
+    int nh = (nblk - 2 + g - 1) / g;
+    const int most = 2 * SPLIT_ROWS; // blocks a helper can hold with two rows per thread
+    nh = std::max(nh, (nblk - 2 + most - 1) / most);
+    return std::min(nh, nblk - 2);
+}
+
+// Plan for blocks-per-helper g; false if it does not fit the device.
+bool plan_split(pimdb_t h, int g, SplitPlan &p) {
+    const int S = h->S;
+    p.nhelp.assign(S, 0);
+    p.per = 1;
+    p.helpers = 0;
+    p.recursion_wgs = 0;
+    for (int s = 0; s < S; ++s) {
+        const int nblk = (int)((h->N[s] + 63) / 64);
+        const int nh = helpers_for(h->N[s], g);
+        p.nhelp[s] = nh;
+        if (nh > 0) {
+            const int own = (nblk - 2 + nh - 1) / nh;
+            p.per = std::max(p.per, (own + SPLIT_ROWS - 1) / SPLIT_ROWS);
+        } else {
+            p.per = std::max(p.per, (int)((h->N[s] + SPLIT_T - 1) / SPLIT_T));
+        }
+        p.helpers += 2 * nh;
+        p.recursion_wgs += 2 + 2 * nh;
+    }
+    if (p.per > 2 || p.helpers == 0) return false;
+    const int occ = exchange_occupancy(h->box > 0 || h->precision == PIMDB_FP64_DIRECT, h->precision == PIMDB_MIXED,
+                                       SPLIT_T, p.per, true);
+    return occ > 0 && (int64_t)p.recursion_wgs <= (int64_t)occ * h->cus;
+}
+
+// The automatic choice: split only when the whole recursions would leave
+// most CUs idle (fewer than one recursion workgroup per two CUs), with the
+// most helpers (smallest g, from 7 blocks each: one per row wave) that fit.
+int auto_split(pimdb_t h, SplitPlan &p) {
+    if (2 * (int64_t)h->S * 2 > h->cus) return 0;
+    for (int g : {7, 14, 28, 56}) {
+        if (plan_split(h, g, p)) return g;
+    }
+    return 0;
+}
+
 // Release the current tables: freed at once, or kept until pimdb_destroy
 // if a graph may hold them.
 void free_tables(pimdb_t h, bool all = false) {
@@ -184,12 +259,33 @@ int build_tables(pimdb_t h) {
     h->status_ws = nullptr;
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, PIMDB_EDEVICE, "cannot select device");
-    if (h->user_threads) {
+    if (!h->cus) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || n <= 0)
+            return fail(h, PIMDB_EDEVICE, "cannot query the compute-unit count");
+        h->cus = n;
+    }
+    // split recursions: the user's blocks per helper, or the automatic choice
+    // (never with an explicit launch shape that is not the split one)
+    SplitPlan plan;
+    h->split_g = 0;
+    if (h->user_split > 0) {
+        if (!plan_split(h, h->user_split, plan))
+            return fail(h, PIMDB_EINVAL, "this split does not fit the device (too many workgroups)");
+        h->split_g = h->user_split;
+    } else if (h->user_split < 0 && !h->user_threads) {
+        h->split_g = auto_split(h, plan);
+    }
+    if (h->split_g > 0) {
+        h->threads = SPLIT_T;
+        h->per_thread = plan.per;
+    } else if (h->user_threads) {
         h->threads = h->user_threads;
         h->per_thread = h->user_per;
     } else {
         auto_tuning(h->Nmax, h->S, h->threads, h->per_thread);
     }
+    h->helpers_total = h->split_g > 0 ? plan.helpers : 0;
     const int T = h->threads;
     const int S = h->S;
     h->desc.assign(S, SysDesc{});
@@ -202,6 +298,7 @@ int build_tables(pimdb_t h) {
         d.N = (int32_t)h->N[s];
         d.P = h->P[s];
         d.nchunk = (int32_t)((h->N[s] + T - 1) / T);
+        d.nhelp = h->split_g > 0 ? plan.nhelp[s] : 0;
         d.beta = h->beta[s];
         d.m = h->m[s];
         d.omegaP = h->omegaP[s];
@@ -211,6 +308,11 @@ int build_tables(pimdb_t h) {
         off += (int64_t)3 * d.P * d.N;
         ws += round_up(WsLayout::total(d.N, d.nchunk), 32);
         st += round_up(StLayout::total(d.N), 32);
+        d.xs = -1;
+        if (d.nhelp > 0) {
+            d.xs = ws;
+            ws += round_up(XsLayout::total((d.N + 63) / 64), 32);
+        }
     }
     h->total_elems = off;
     h->ws_doubles = ws;
@@ -221,12 +323,19 @@ int build_tables(pimdb_t h) {
     std::vector<int> order(S);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return h->N[a] > h->N[b]; });
+    // (split systems: both chains, then their helpers)
     std::vector<Item> fb, f, b, sp;
     for (int s : order) {
         fb.push_back(Item{s, ROLE_FORWARD, 0, 0});
         fb.push_back(Item{s, ROLE_BACKWARD, 0, 0});
         f.push_back(Item{s, ROLE_FORWARD, 0, 0});
         b.push_back(Item{s, ROLE_BACKWARD, 0, 0});
+        for (int x = 0; x < h->desc[s].nhelp; ++x) {
+            fb.push_back(Item{s, ROLE_FHELP, x, 0});
+            fb.push_back(Item{s, ROLE_BHELP, x, 0});
+            f.push_back(Item{s, ROLE_FHELP, x, 0});
+            b.push_back(Item{s, ROLE_BHELP, x, 0});
+        }
     }
     for (int s : order)
         for (int c = 0; c < h->desc[s].nchunk; ++c) sp.push_back(Item{s, ROLE_SPRINGS, c, 0});
@@ -291,6 +400,7 @@ LaunchArgs base_args(pimdb_t h, char *ws) {
     a.trap_w2 = h->trap_w * h->trap_w;
     a.mixed = h->precision == PIMDB_MIXED;
     a.direct = h->precision == PIMDB_FP64_DIRECT;
+    a.wait_ticks = h->wait_ticks;
     return a;
 }
 
@@ -306,11 +416,17 @@ int run(pimdb_t h, LaunchArgs &a, const Item *items, int n) {
     h->status_ws = (char *)a.flags;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(h->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) h->captured = true;
+    const bool tm = h->timing && cs == hipStreamCaptureStatusNone;
     a.items = items;
-    hipError_t e = launch_exchange(a, n, h->threads, h->per_thread, h->stream);
+    hipError_t e;
+    if (tm && (e = hipEventRecord(h->ev[0], h->stream)) != hipSuccess) return hip_fail(h, e, "event");
+    e = launch_exchange(a, n, h->threads, h->per_thread, h->split_g > 0, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "exchange launch");
+    if (tm && (e = hipEventRecord(h->ev[1], h->stream)) != hipSuccess) return hip_fail(h, e, "event");
     e = launch_finalize(a, h->S, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "finalize launch");
+    if (tm && (e = hipEventRecord(h->ev[2], h->stream)) != hipSuccess) return hip_fail(h, e, "event");
+    h->ev_recorded = tm;
     return PIMDB_OK;
 }
 
@@ -356,6 +472,12 @@ int pimdb_create(pimdb_t *out, int device, void *stream) {
     if (!h) return PIMDB_EDEVICE;
     h->device = device;
     h->stream = (hipStream_t)stream;
+    // the split recursions' wait limit in microseconds (tests of the timeout
+    // path shorten it so that waits give up at once)
+    if (const char *w = std::getenv("PIMDB_SPLIT_WAIT_US")) {
+        const long long us = std::atoll(w);
+        if (us >= 0) h->wait_ticks = (uint64_t)us * 100;
+    }
     {
         DeviceGuard g(device);
         if (!g.ok) {
@@ -374,6 +496,8 @@ int pimdb_destroy(pimdb_t h) {
         DeviceGuard g(h->device);
         (void)hipStreamSynchronize(h->stream);
         free_tables(h, true);
+        for (hipEvent_t &e : h->ev)
+            if (e) (void)hipEventDestroy(e);
     }
     delete h;
     return PIMDB_OK;
@@ -434,6 +558,57 @@ int pimdb_set_tuning(pimdb_t h, int threads, int per_thread) {
     return PIMDB_OK;
 }
 
+int pimdb_set_timing(pimdb_t h, int enable) {
+    if (!h) return PIMDB_EINVAL;
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, PIMDB_EDEVICE, "cannot select device");
+    if (enable && !h->ev[0]) {
+        for (hipEvent_t &e : h->ev) {
+            const hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return hip_fail(h, r, "hipEventCreate");
+        }
+    }
+    h->timing = enable != 0;
+    h->ev_recorded = false;
+    return PIMDB_OK;
+}
+
+int pimdb_last_timing(pimdb_t h, float *exchange_ms, float *finalize_ms) {
+    if (!h || !exchange_ms || !finalize_ms) return PIMDB_EINVAL;
+    if (!h->ev_recorded) return fail(h, PIMDB_ENOSYS, "no timed evaluation recorded");
+    DeviceGuard g(h->device);
+    hipError_t e;
+    if ((e = hipEventSynchronize(h->ev[2])) != hipSuccess) return hip_fail(h, e, "event sync");
+    if ((e = hipEventElapsedTime(exchange_ms, h->ev[0], h->ev[1])) != hipSuccess) return hip_fail(h, e, "event time");
+    if ((e = hipEventElapsedTime(finalize_ms, h->ev[1], h->ev[2])) != hipSuccess) return hip_fail(h, e, "event time");
+    return PIMDB_OK;
+}
+
+int pimdb_set_split(pimdb_t h, int blocks_per_helper) {
+    if (!h) return PIMDB_EINVAL;
+    if (blocks_per_helper < -1) return fail(h, PIMDB_EINVAL, "blocks per helper must be -1, 0 or positive");
+    const int old = h->user_split;
+    h->user_split = blocks_per_helper;
+    if (h->S > 0) {
+        const int rc = build_tables(h);
+        if (rc != PIMDB_OK) {
+            const std::string msg = h->last_error;
+            h->user_split = old;
+            (void)build_tables(h);
+            h->last_error = msg;
+            return rc;
+        }
+    }
+    return PIMDB_OK;
+}
+
+int pimdb_get_split(pimdb_t h, int *blocks_per_helper, int *helpers) {
+    if (!h || !blocks_per_helper || !helpers) return PIMDB_EINVAL;
+    *blocks_per_helper = h->split_g;
+    *helpers = h->helpers_total;
+    return PIMDB_OK;
+}
+
 int pimdb_get_tuning(pimdb_t h, int *threads, int *per_thread) {
     if (!h || !threads || !per_thread) return PIMDB_EINVAL;
     *threads = h->threads;
@@ -468,9 +643,10 @@ int pimdb_bind_workspace(pimdb_t h, void *dev_ptr, size_t bytes) {
     h->status_ws = h->ws;
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, PIMDB_EDEVICE, "cannot select device");
-    const int64_t nints = WS_HEADER_BYTES / 4;
-    const int64_t lim = (int64_t)bytes / 4;
-    hipError_t e = launch_clear((int32_t *)dev_ptr, std::min(nints, lim), h->stream);
+    // the status word and the split recursions' flags start at zero
+    const int64_t need = h->S > 0 ? (int64_t)ws_bytes_needed(h) : WS_HEADER_BYTES;
+    const int64_t nints = std::min<int64_t>(need, (int64_t)bytes) / 4;
+    hipError_t e = launch_clear((int32_t *)dev_ptr, nints, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "clear workspace");
     return PIMDB_OK;
 }
@@ -534,6 +710,11 @@ int pimdb_exchange_forces_static(pimdb_t h, const double *pos, double *forces, d
     a.out = forces;
     a.energy = energy;
     a.mode = M_FWD | M_BWD | M_WSUM | M_FORCES | (energy ? M_ENERGY : 0);
+    if (h->split_g > 0) { // the scratch holds the last call's contents, maybe of another layout
+        DeviceGuard g(h->device);
+        const hipError_t e = launch_clear_flags(a, h->S, h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "clear flags");
+    }
     return run(h, a, items_fb(h), h->n_fb);
 }
 

@@ -18,7 +18,7 @@ constexpr int EMIN = -(1 << 30);         // exponent of an empty accumulator
 constexpr int EZ_LIM = 1 << 29;          // bound on the exponent of a published Z value
 constexpr int EMASK = -(3 << 29);        // term exponent that adds nothing (below EMIN)
 
-enum StatusBits { ST_NONFINITE_IN = 1, ST_NONFINITE_OUT = 2, ST_RANGE = 4, ST_PRECISION = 8 };
+enum StatusBits { ST_NONFINITE_IN = 1, ST_NONFINITE_OUT = 2, ST_RANGE = 4, ST_PRECISION = 8, ST_TIMEOUT = 16 };
 // |kappa| max |p - o|^2 up to which the open FP64 dot form keeps the 1e-10
 // accuracy with margin (measured 4e-12 in the forces at 2.5e6)
 constexpr double DOT_LIM = 8388608.0; // 2^23
@@ -27,9 +27,16 @@ constexpr double DOT_LIM = 8388608.0; // 2^23
 // error 2.1e-16, about one rounding; coefficients from gen_exp2_coeffs.py),
 // highest degree first.  Kept in constant memory so the wave-uniform
 // coefficients live in scalar registers and every Horner step is one
-// v_fma_f64.
+// v_fma_f64.  The array has external linkage, so the compiler cannot fold
+// the values into 64-bit literals (each would take two VGPRs); every
+// translation unit names its own copy (PIMDB_EXP2_SYM) so the host-side
+// shadows of the copies do not collide at link time.
+#ifndef PIMDB_EXP2_SYM
+#define PIMDB_EXP2_SYM exp2_c_misc
+#endif
+#define EXP2_C PIMDB_EXP2_SYM
 constexpr int EXP2_N = 11;
-static __constant__ double EXP2_C[EXP2_N] = {
+__constant__ double EXP2_C[EXP2_N] = {
     7.037278846726901e-09,  1.0208537929657404e-07, 1.3215662835959238e-06, 1.5252658116409854e-05,
     0.00015403529961127076, 0.0013333558228561767,  0.009618129108034596,   0.05550410866445883,
     0.24022650695908768,    0.6931471805599497,     1.0};

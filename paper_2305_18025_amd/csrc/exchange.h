@@ -127,6 +127,9 @@ constexpr int KTRI = BK * (BK + 1) / 2;
 //                      lanes a step does not reach hold EMASK (filled once)
 //   [L_PA, +KSPLIT*4*BK)  partial sums {A, Wx, Wy, Wz} per wave and lane
 //   [L_PE, +KSPLIT*BK/2)  their exponents (ints)
+//   [L_DL, +4*BK+BK/2) the accumulator a helper delivered for the block
+//                      (split recursions' chain workgroup)
+//   [L_ABT, +1)        abort flag of a split recursion (int)
 //   [LDS_RED, +T)      block reduction scratch of the spring role (a
 //                      workgroup runs either a recursion or springs, so
 //                      this aliases the recursion regions)
@@ -140,7 +143,9 @@ constexpr int L_KP = L_ZL + 3 * BS;
 constexpr int L_KN = L_KP + KTRI;
 constexpr int L_PA = L_KN + BK * BK / 2;
 constexpr int L_PE = L_PA + KSPLIT * 4 * BK;
-constexpr int L_END = L_PE + KSPLIT * BK / 2;
+constexpr int L_DL = L_PE + KSPLIT * BK / 2; // delivered accumulator {A, Wx, Wy, Wz} x 64 and exponents
+constexpr int L_ABT = L_DL + 4 * BK + BK / 2;  // abort flag (int) of a split recursion
+constexpr int L_END = L_ABT + 1;
 constexpr int LDS_RED = 0;
 
 __device__ __forceinline__ double *stg_block(double *sm, int b) { return sm + L_STG + ((b % 3) * BS + 1) * STG; }
@@ -779,11 +784,13 @@ __device__ __forceinline__ void wave_dispatch(Rows<JJ> &R, const RecCtx &c, int 
     }
 }
 
-template <bool FWD, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool MAG>
-__device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c) {
-    const int t = c.t, T = c.T, N = c.N, W = c.W, w = t >> 6, nblk = c.nblk;
-    const size_t NN = c.NN;
-    double *zm_out, *ze_out, *r_out;
+// Where a recursion writes its results: the forward Z_f, Z_b mantissas and
+// exponents and the weighted mean displacements (workspace, or the adjoint
+// state when the forward half saves them).
+template <bool FWD>
+__device__ __forceinline__ void rec_outputs(const LaunchArgs &a, const SysDesc &sd, double *&zm_out, double *&ze_out,
+                                            double *&r_out) {
+    const int N = sd.N;
     if (FWD) {
         double *base = (a.mode & M_SAVE) ? a.state + sd.st : a.ws + sd.ws;
         zm_out = base + ((a.mode & M_SAVE) ? StLayout::zf_m(N) : WsLayout::zf_m(N));
@@ -795,35 +802,45 @@ __device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDes
         ze_out = base + WsLayout::zb_e(N);
         r_out = base + WsLayout::rb(N);
     }
-    Rows<JJ> R;
-    bool range_bad = false;
-#pragma unroll
-    for (int j = 0; j < JJ; ++j) {
-        const int q = j * T + t;
-        R.px[j] = R.py[j] = R.pz[j] = R.hl[j] = 0.0;
-        if (q < N) {
-            if (FWD) {
-                R.px[j] = c.bP[q];
-                R.py[j] = c.bP[NN + q];
-                R.pz[j] = c.bP[2 * NN + q];
-                const int r = q < N - 1 ? q + 1 : q;
-                R.hl[j] = -c.kap * sqlen<MIXED>(mimg<BOX>(R.px[j] - c.b1[r], c.box, c.ib),
-                                                 mimg<BOX>(R.py[j] - c.b1[NN + r], c.box, c.ib),
-                                                 mimg<BOX>(R.pz[j] - c.b1[2 * NN + r], c.box, c.ib));
-                range_bad |= !(R.hl[j] <= XHI);
-            } else {
-                R.px[j] = c.b1[q];
-                R.py[j] = c.b1[NN + q];
-                R.pz[j] = c.b1[2 * NN + q];
-            }
-            if (!BOX && !MIXED)
-                dot_row(c.kap, R.px[j] - c.ox, R.py[j] - c.oy, R.pz[j] - c.oz, R.hl[j], R.px[j], R.py[j], R.pz[j],
-                        R.hl[j]);
+}
+
+// Row j of R holds accumulator q (0 <= q < N, or an unused row): its point
+// (forward bead P of q with h_q, backward bead 1 of q) in the form the
+// terms use, and an empty accumulator.
+template <bool FWD, int JJ, bool BOX, bool MIXED>
+__device__ __forceinline__ void load_row(Rows<JJ> &R, int j, const RecCtx &c, int q, bool &range_bad) {
+    const int N = c.N;
+    const size_t NN = c.NN;
+    R.px[j] = R.py[j] = R.pz[j] = R.hl[j] = 0.0;
+    if (q >= 0 && q < N) {
+        if (FWD) {
+            R.px[j] = c.bP[q];
+            R.py[j] = c.bP[NN + q];
+            R.pz[j] = c.bP[2 * NN + q];
+            const int r = q < N - 1 ? q + 1 : q;
+            R.hl[j] = -c.kap * sqlen<MIXED>(mimg<BOX>(R.px[j] - c.b1[r], c.box, c.ib),
+                                             mimg<BOX>(R.py[j] - c.b1[NN + r], c.box, c.ib),
+                                             mimg<BOX>(R.pz[j] - c.b1[2 * NN + r], c.box, c.ib));
+            range_bad |= !(R.hl[j] <= XHI);
+        } else {
+            R.px[j] = c.b1[q];
+            R.py[j] = c.b1[NN + q];
+            R.pz[j] = c.b1[2 * NN + q];
         }
-        R.a[j] = Acc{0.0, 0.0, 0.0, 0.0, EMIN};
+        if (!BOX && !MIXED)
+            dot_row(c.kap, R.px[j] - c.ox, R.py[j] - c.oy, R.pz[j] - c.oz, R.hl[j], R.px[j], R.py[j], R.pz[j],
+                    R.hl[j]);
     }
-    // first block staged, first broadcast value: Z_f[0] = 1 (V^[1,0] = 0),
-    // or Z_b[N+1] / N = 1 / N
+    R.a[j] = Acc{0.0, 0.0, 0.0, 0.0, EMIN};
+}
+
+// Before the first block of a serial recursion: stage the first block,
+// publish the first broadcast value (Z_f[0] = 1 since V^[1,0] = 0, or
+// Z_b[N+1] / N = 1 / N), write the fixed ends of the outputs and fill the
+// diagonal triangle's LDS (see the LDS map).  Ends with a barrier.
+template <bool FWD, bool BOX, bool MIXED>
+__device__ __forceinline__ void rec_prologue(const RecCtx &c, double *zm_out, double *ze_out, bool &range_bad) {
+    const int t = c.t, T = c.T, N = c.N, w = t >> 6, nblk = c.nblk;
     const int b0 = FWD ? 0 : nblk - 1;
     const int s0 = FWD ? 0 : N - 1;
     if (w == 0) {
@@ -847,13 +864,24 @@ __device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDes
             ze_out[N + 1] = 0.0;
         }
     }
-    // the diagonal triangle's fills (see the LDS map)
     for (int i = t; i < BK * BK; i += T) kn_base(c.sm)[i] = EMASK;
     for (int i = t; i < KTRI; i += T) c.sm[L_KP + i] = 0.0;
     // loads of the rows are complete before the loop (a wait inside it would
     // also wait for the staging loads issued there)
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+}
+
+template <bool FWD, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool MAG>
+__device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c) {
+    const int t = c.t, T = c.T, W = c.W, w = t >> 6, nblk = c.nblk;
+    double *zm_out, *ze_out, *r_out;
+    rec_outputs<FWD>(a, sd, zm_out, ze_out, r_out);
+    Rows<JJ> R;
+    bool range_bad = false;
+#pragma unroll
+    for (int j = 0; j < JJ; ++j) load_row<FWD, JJ, BOX, MIXED>(R, j, c, j * T + t, range_bad);
+    rec_prologue<FWD, BOX, MIXED>(c, zm_out, ze_out, range_bad);
     for (int it = 0; it < nblk; ++it) {
         const int k = FWD ? it : nblk - 1 - it;
         const int prev = FWD ? k - 1 : k + 1;
@@ -889,6 +917,295 @@ __device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDes
     if (range_bad) set_flag(a.flags, ST_RANGE);
 }
 
+
+// ------------------------------------------------------- split recursions
+// For small batches one workgroup per recursion leaves most CUs idle, so a
+// system's recursion may be spread over 1 + H workgroups (nhelp = H):
+//  - the chain workgroup runs phase A of every block k (the triangle's
+//    exponentials; the previous block's terms for block k's accumulators)
+//    and the block's serial steps, and publishes the block's step values
+//    (what the panels use) to the exchange area;
+//  - helper h owns the accumulators of every H-th block from 2 + h up
+//    (forward; backward from nblk - 3 - h down).  For every published block
+//    i it adds block i's terms to its accumulators of blocks at least two
+//    blocks further in recursion order, and the accumulator of the block
+//    exactly two further then holds every term but those of the next block
+//    (which the chain adds in its phase A): it is delivered to the chain.
+// A delivery for block k is made while the chain runs block k - 1, so the
+// hand-over latency stays off the serial path.  Flags and payloads are
+// device-scope relaxed atomics, which bypass the caches that are not
+// coherent across the XCDs without flushing them; a producer waits for its
+// payload stores to complete before it stores the flag.  Every wait is
+// bounded in time: on expiry it sets ST_TIMEOUT and the workgroup returns.
+// The host keeps a split launch within the workgroups that are resident at
+// once, so no wait depends on a workgroup that has not started.
+
+__device__ __forceinline__ void st_dev(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(int *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_dev(const int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One wave spins until *flag is set; false (and ST_TIMEOUT) after `ticks`
+// of the 100 MHz constant clock.
+__device__ __forceinline__ bool wave_wait(const int *flag, int32_t *status, uint64_t ticks) {
+    const uint64_t t0 = wall_clock64();
+    while (__builtin_amdgcn_readfirstlane(ld_dev(flag)) == 0) {
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t0 > ticks) {
+            if ((threadIdx.x & 63) == 0) set_flag(status, ST_TIMEOUT);
+            return false;
+        }
+    }
+    return true;
+}
+
+// After the wave's payload stores: wait for them, then set the flag.
+__device__ __forceinline__ void wave_signal(int *flag) {
+    __builtin_amdgcn_s_waitcnt(0);
+    if ((threadIdx.x & 63) == 0) st_dev(flag, 1);
+}
+
+struct XsPtrs {
+    double *pub_zl;
+    int *pub_ze;
+    double *del_acc;
+    int *del_e;
+    int *pub_flag, *del_flag;
+};
+
+template <bool FWD>
+__device__ __forceinline__ XsPtrs xs_ptrs(const LaunchArgs &a, const SysDesc &sd, int nblk) {
+    const int d = FWD ? 0 : 1;
+    double *x = a.ws + sd.xs;
+    int *fl = (int *)(x + XsLayout::flags(nblk));
+    return XsPtrs{x + XsLayout::pub_zl(nblk, d), (int *)(x + XsLayout::pub_ze(nblk, d)),
+                  x + XsLayout::del_acc(nblk, d), (int *)(x + XsLayout::del_e(nblk, d)),
+                  fl + (2 * d) * nblk, fl + (2 * d + 1) * nblk};
+}
+
+// Chain workgroup of a split recursion (no accumulator rows of its own).
+template <bool FWD, bool BOX, bool MIXED, bool WSUM>
+__device__ __forceinline__ void chain_rows(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c) {
+    constexpr bool DOT = !BOX && !MIXED;
+    const int t = c.t, W = c.W, w = t >> 6, lane = t & 63, nblk = c.nblk;
+    double *zm_out, *ze_out, *r_out;
+    rec_outputs<FWD>(a, sd, zm_out, ze_out, r_out);
+    const XsPtrs X = xs_ptrs<FWD>(a, sd, nblk);
+    int *abort_flag = (int *)(c.sm + L_ABT);
+    if (t == 0) *abort_flag = 0;
+    bool range_bad = false;
+    rec_prologue<FWD, BOX, MIXED>(c, zm_out, ze_out, range_bad);
+    for (int it = 0; it < nblk; ++it) {
+        const int k = FWD ? it : nblk - 1 - it;
+        const int prev = FWD ? k - 1 : k + 1;
+        const bool has_prev = FWD ? k > 0 : k + 1 < nblk;
+        // blocks two or more steps into the recursion come with the sum of
+        // all but their previous block's terms from a helper
+        const bool delivered = FWD ? k >= 2 : k <= nblk - 3;
+        const int nb = FWD ? k + 1 : k - 1;
+        const bool last = w == W - 1;
+        Stage g{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (last && nb >= 0 && nb < nblk) g = stage_load<BOX, MIXED>(c, nb, range_bad);
+        diag_terms<FWD, BOX, MIXED>(c, k);
+        if (has_prev) {
+            __builtin_amdgcn_s_setprio(1);
+            diag_partial<FWD, BOX, MIXED, WSUM, false>(c, k, prev);
+            __builtin_amdgcn_s_setprio(0);
+        }
+        if (last) {
+            if (delivered) { // fetch the delivered accumulator into LDS
+                if (wave_wait(X.del_flag + k, a.flags, a.wait_ticks)) {
+                    double *D = c.sm + L_DL;
+                    const double *src = X.del_acc + (size_t)k * 4 * BK + lane;
+                    D[lane] = ld_dev(src);
+                    D[BK + lane] = ld_dev(src + BK);
+                    D[2 * BK + lane] = ld_dev(src + 2 * BK);
+                    D[3 * BK + lane] = ld_dev(src + 3 * BK);
+                    ((int *)(D + 4 * BK))[lane] = ld_dev(X.del_e + (size_t)k * BK + lane);
+                } else if (lane == 0) {
+                    *abort_flag = 1;
+                }
+            }
+            if (nb >= 0 && nb < nblk) stage_store(c, nb, g);
+        }
+        __syncthreads();
+        if (*abort_flag) return;
+        if (w == k % W) {
+            const double *me = stg_block(c.sm, k) + STG * lane;
+            Rows<1> R;
+            if (FWD) {
+                R.px[0] = me[3];
+                R.py[0] = me[4];
+                R.pz[0] = me[5];
+                R.hl[0] = me[6];
+            } else {
+                R.px[0] = me[0];
+                R.py[0] = me[1];
+                R.pz[0] = me[2];
+                R.hl[0] = 0.0;
+            }
+            if (DOT) dot_row(c.kap, R.px[0], R.py[0], R.pz[0], R.hl[0], R.px[0], R.py[0], R.pz[0], R.hl[0]);
+            R.a[0] = Acc{0.0, 0.0, 0.0, 0.0, EMIN};
+            if (delivered) {
+                const double *D = c.sm + L_DL;
+                R.a[0] = Acc{D[lane], D[BK + lane], D[2 * BK + lane], D[3 * BK + lane], ((const int *)(D + 4 * BK))[lane]};
+            }
+            __builtin_amdgcn_s_setprio(2);
+            diagonal<FWD, 0, 1, BOX, MIXED, WSUM, true>(R, c, k, has_prev, zm_out, ze_out, r_out);
+            __builtin_amdgcn_s_setprio(0);
+            // the block's step values for the helpers
+            st_dev(X.pub_zl + (size_t)k * BK + lane, zl_block(c.sm, k)[lane]);
+            st_dev(X.pub_ze + (size_t)k * BK + lane, ze_block(c.sm, k)[lane]);
+            wave_signal(X.pub_flag + k);
+        }
+        __syncthreads();
+    }
+    if (range_bad) set_flag(a.flags, ST_RANGE);
+}
+
+// Helper blocks, ascending: b(m) = b0 + m H for m < nown (forward b0 = 2 + h;
+// backward every H-th block from nblk - 3 - h down to the smallest, b0).
+__device__ __forceinline__ void helper_blocks(bool fwd, int nblk, int H, int h, int &b0, int &nown) {
+    if (fwd) {
+        b0 = 2 + h;
+        nown = b0 < nblk ? (nblk - 1 - b0) / H + 1 : 0;
+    } else {
+        const int top = nblk - 3 - h;
+        b0 = top >= 0 ? top % H : 0;
+        nown = top >= 0 ? (top - b0) / H + 1 : 0;
+    }
+}
+
+// One wave's work on published block i: the panel over its live rows;
+// when it holds the block two further in recursion order (URG: row LO
+// forward, HI - 1 backward), that row first, and its accumulator is then
+// delivered.
+template <bool FWD, int LO, int HI, bool URG, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool MAG>
+__device__ __forceinline__ void helper_iter(Rows<JJ> &R, const RecCtx &c, int i, const XsPtrs &X) {
+    if constexpr (URG) {
+        constexpr int ju = FWD ? LO : HI - 1;
+        const int lane = c.t & 63;
+        panel<FWD, ju, ju + 1, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i);
+        const int b = FWD ? i + 2 : i - 2;
+        double *dst = X.del_acc + (size_t)b * 4 * BK + lane;
+        st_dev(dst, R.a[ju].A);
+        st_dev(dst + BK, R.a[ju].Wx);
+        st_dev(dst + 2 * BK, R.a[ju].Wy);
+        st_dev(dst + 3 * BK, R.a[ju].Wz);
+        st_dev(X.del_e + (size_t)b * BK + lane, R.a[ju].e);
+        wave_signal(X.del_flag + b);
+        if (FWD)
+            panel<FWD, LO + 1, HI, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i);
+        else
+            panel<FWD, LO, HI - 1, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i);
+    } else {
+        panel<FWD, LO, HI, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i);
+    }
+}
+
+template <bool FWD, int X_, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool MAG>
+__device__ __forceinline__ void helper_dispatch(Rows<JJ> &R, const RecCtx &c, int i, int x, bool urg,
+                                                const XsPtrs &X) {
+    if constexpr (X_ <= JJ) {
+        if (x == X_) {
+            if (FWD) {
+                if constexpr (X_ < JJ) {
+                    if (urg)
+                        helper_iter<FWD, X_, JJ, true, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, X);
+                    else
+                        helper_iter<FWD, X_, JJ, false, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, X);
+                }
+            } else {
+                if constexpr (X_ > 0) {
+                    if (urg)
+                        helper_iter<FWD, 0, X_, true, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, X);
+                    else
+                        helper_iter<FWD, 0, X_, false, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, X);
+                }
+            }
+        } else {
+            helper_dispatch<FWD, X_ + 1, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, x, urg, X);
+        }
+    }
+}
+
+// The fetch wave of a helper (its last wave, which holds no rows) copies
+// published block i into the LDS ring: its points (loaded before the flag
+// is seen) and its step values.  False after a wait timed out.
+template <bool BOX, bool MIXED>
+__device__ __forceinline__ bool helper_fetch(const LaunchArgs &a, const RecCtx &c, const XsPtrs &X, int i) {
+    const int lane = c.t & 63;
+    bool unused = false;
+    const Stage g = stage_load<BOX, MIXED>(c, i, unused);
+    if (!wave_wait(X.pub_flag + i, a.flags, a.wait_ticks)) return false;
+    zl_block(c.sm, i)[lane] = ld_dev(X.pub_zl + (size_t)i * BK + lane);
+    ze_block(c.sm, i)[lane] = ld_dev(X.pub_ze + (size_t)i * BK + lane);
+    stage_store(c, i, g);
+    return true;
+}
+
+// Helper h of a split recursion: row j of wave w < W - 1 holds its block
+// b(j (W - 1) + w); the last wave fetches the published blocks one ahead of
+// the panels, so the wait and the loads overlap the arithmetic.
+template <bool FWD, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool MAG>
+__device__ __forceinline__ void helper_rows(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c, int h) {
+    const int t = c.t, w = t >> 6, lane = t & 63, nblk = c.nblk, H = sd.nhelp;
+    const int WR = c.W - 1; // row waves
+    int b0, nown;
+    helper_blocks(FWD, nblk, H, h, b0, nown);
+    if (nown == 0) return;
+    const XsPtrs X = xs_ptrs<FWD>(a, sd, nblk);
+    int *abort_flag = (int *)(c.sm + L_ABT);
+    Rows<JJ> R;
+    bool range_bad = false;
+#pragma unroll
+    for (int j = 0; j < JJ; ++j) {
+        const int m = j * WR + w;
+        load_row<FWD, JJ, BOX, MIXED>(R, j, c, (w < WR && m < nown) ? (b0 + m * H) * BK + lane : -1, range_bad);
+    }
+    // published blocks that some row still needs, in recursion order
+    const int blast = b0 + (nown - 1) * H;
+    const int i_begin = FWD ? 0 : nblk - 1;
+    const int i_end = FWD ? blast - 2 : b0 + 2; // inclusive
+    const int di = FWD ? 1 : -1;
+    if (t == 0) *abort_flag = 0;
+    __syncthreads();
+    if (w == WR && !helper_fetch<BOX, MIXED>(a, c, X, i_begin) && lane == 0) *abort_flag = 1;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int i = i_begin; FWD ? i <= i_end : i >= i_end; i += di) {
+        if (*abort_flag) return;
+        if (w == WR) {
+            if (i != i_end && !helper_fetch<BOX, MIXED>(a, c, X, i + di) && lane == 0) *abort_flag = 1;
+        } else {
+            int x;
+            bool urg;
+            if (FWD) { // live: blocks >= i + 2, i.e. m >= m0
+                const int m0 = i <= h ? 0 : (i - h + H - 1) / H;
+                urg = i >= h && (i - h) % H == 0;
+                x = m0 <= w ? 0 : (m0 - w + WR - 1) / WR;
+                urg = urg && x * WR + w == m0;
+            } else { // live: blocks <= i - 2, i.e. m < L
+                const int L = i - 2 >= b0 ? min((i - 2 - b0) / H + 1, nown) : 0;
+                urg = i - 2 >= b0 && (i - 2 - b0) % H == 0;
+                x = L - 1 >= w ? min((L - 1 - w) / WR + 1, JJ) : 0;
+                urg = urg && x > 0 && (x - 1) * WR + w == L - 1;
+            }
+            helper_dispatch<FWD, 0, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, x, urg, X);
+        }
+        __syncthreads();
+    }
+    if (range_bad) set_flag(a.flags, ST_RANGE);
+}
+
 // Dispatch on the number of rows the system needs, JJ = ceil(N / T) <= J,
 // so that no thread carries rows past the end of a smaller system.
 // The one-row kernels round term exponents with the row constant (MAG)
@@ -909,6 +1226,26 @@ __device__ __forceinline__ void rec_dispatch(const LaunchArgs &a, const SysDesc 
             }
         } else {
             rec_dispatch<JJ + 1, J, FWD, BOX, MIXED, WSUM>(a, sd, c, jj, wrap_ok);
+        }
+    }
+}
+
+// Helpers: JJ = rows per thread the helper needs (its blocks over the waves).
+template <int JJ, int J, bool FWD, bool BOX, bool MIXED, bool WSUM>
+__device__ __forceinline__ void help_dispatch(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c, int h, int jj,
+                                              bool wrap_ok) {
+    if constexpr (JJ <= J) {
+        if (jj == JJ) {
+            if constexpr (J == 1) {
+                if (wrap_ok)
+                    helper_rows<FWD, JJ, BOX, MIXED, WSUM, true, true>(a, sd, c, h);
+                else
+                    helper_rows<FWD, JJ, BOX, MIXED, WSUM, true, false>(a, sd, c, h);
+            } else {
+                helper_rows<FWD, JJ, BOX, MIXED, WSUM, (J <= 2), false>(a, sd, c, h);
+            }
+        } else {
+            help_dispatch<JJ + 1, J, FWD, BOX, MIXED, WSUM>(a, sd, c, h, jj, wrap_ok);
         }
     }
 }
@@ -946,8 +1283,10 @@ __device__ __forceinline__ void system_extent(const RecCtx &c, double &r1, doubl
     }
 }
 
-template <int J, bool FWD, bool BOX, bool MIXED, bool WSUM>
-__device__ __forceinline__ void recursion_role(const LaunchArgs &a, const SysDesc sd, double *sm) {
+// A recursion workgroup: the whole recursion (nhelp = 0), the chain of a
+// split recursion (helper < 0), or helper `helper` of one.
+template <int J, bool FWD, bool BOX, bool MIXED, bool WSUM, bool SPLIT>
+__device__ __forceinline__ void recursion_role(const LaunchArgs &a, const SysDesc sd, double *sm, int helper) {
     RecCtx c;
     c.sm = sm;
     c.NN = (size_t)sd.N;
@@ -981,6 +1320,19 @@ __device__ __forceinline__ void recursion_role(const LaunchArgs &a, const SysDes
     if (BOX && a.box > 0) D = fmin(D, 0.8660254037844387 * a.box);
     const bool wrap_ok = -sd.kappa * D * D <= 1073741824.0; // 2^30
     if (!BOX && !MIXED && c.t == 0 && -sd.kappa * fmax(r1, rP) > DOT_LIM) set_flag(a.flags, ST_PRECISION);
+    if constexpr (SPLIT) {
+        if (sd.nhelp > 0 && helper < 0) {
+            chain_rows<FWD, BOX, MIXED, WSUM>(a, sd, c);
+            return;
+        }
+        if (sd.nhelp > 0) {
+            int b0, nown;
+            helper_blocks(FWD, c.nblk, sd.nhelp, helper, b0, nown);
+            const int jj = max(1, (nown + c.W - 2) / (c.W - 1)); // rows on the W - 1 row waves
+            help_dispatch<1, J, FWD, BOX, MIXED, WSUM>(a, sd, c, helper, jj, wrap_ok);
+            return;
+        }
+    }
     const int jj = (sd.N + c.T - 1) / c.T;
     rec_dispatch<1, J, FWD, BOX, MIXED, WSUM>(a, sd, c, jj, wrap_ok);
 }
@@ -1075,7 +1427,7 @@ __device__ __forceinline__ void springs_role(const LaunchArgs &a, const SysDesc 
 // the results of all workgroups are visible to it through the stream order
 // alone: no grid-wide flag, and no device-scope cache maintenance per
 // workgroup.
-template <int J, bool BOX, bool MIXED>
+template <int J, bool BOX, bool MIXED, bool SPLIT>
 __device__ __forceinline__ void exchange_body(const LaunchArgs &a) {
     extern __shared__ double sm[];
     const Item it = a.items[blockIdx.x];
@@ -1087,13 +1439,14 @@ __device__ __forceinline__ void exchange_body(const LaunchArgs &a) {
             return;
         }
     }
-    if (it.role == ROLE_FORWARD) {
+    if (it.role == ROLE_FORWARD || it.role == ROLE_FHELP) {
+        const int helper = it.role == ROLE_FHELP ? it.idx : -1;
         if (a.mode & M_WSUM)
-            recursion_role<J, true, BOX, MIXED, true>(a, sd, sm);
+            recursion_role<J, true, BOX, MIXED, true, SPLIT>(a, sd, sm, helper);
         else
-            recursion_role<J, true, BOX, MIXED, false>(a, sd, sm);
-    } else if (it.role == ROLE_BACKWARD) {
-        recursion_role<J, false, BOX, MIXED, true>(a, sd, sm);
+            recursion_role<J, true, BOX, MIXED, false, SPLIT>(a, sd, sm, helper);
+    } else if (it.role == ROLE_BACKWARD || it.role == ROLE_BHELP) {
+        recursion_role<J, false, BOX, MIXED, true, SPLIT>(a, sd, sm, it.role == ROLE_BHELP ? it.idx : -1);
     } else {
         // 1024-thread kernels have 128 registers: smaller bead groups
         springs_role<BOX, (J >= 4 ? 8 : 4)>(a, sd, it.sys, it.idx, sm);
@@ -1104,12 +1457,19 @@ __device__ __forceinline__ void exchange_body(const LaunchArgs &a) {
 // J = 8 need the 512-thread bound to avoid spilling.
 template <int J, bool BOX, bool MIXED>
 __global__ void __launch_bounds__(1024) k_exchange(LaunchArgs a) {
-    exchange_body<J, BOX, MIXED>(a);
+    exchange_body<J, BOX, MIXED, false>(a);
 }
 
 template <int J, bool BOX, bool MIXED>
 __global__ void __launch_bounds__(512) k_exchange_wide(LaunchArgs a) {
-    exchange_body<J, BOX, MIXED>(a);
+    exchange_body<J, BOX, MIXED, false>(a);
+}
+
+// Launches with split recursions (some systems spread over helper
+// workgroups); 512 threads, so that two workgroups share a CU.
+template <int J, bool BOX, bool MIXED>
+__global__ void __launch_bounds__(512) k_exchange_split(LaunchArgs a) {
+    exchange_body<J, BOX, MIXED, true>(a);
 }
 
 // LDS of one fused workgroup: the recursion regions, or the springs role's

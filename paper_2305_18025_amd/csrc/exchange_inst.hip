@@ -3,27 +3,55 @@
 // minimum image) and PIMDB_MIXED (FP32 compensated pair lengths).  The build
 // compiles this file once per variant, in parallel; kernels.hip dispatches
 // to the variant a launch needs.
-#include "exchange.h"
-
 #if !defined(PIMDB_J) || !defined(PIMDB_BOX) || !defined(PIMDB_MIXED)
 #error "compile with -DPIMDB_J=<1|2|4|8> -DPIMDB_BOX=<0|1> -DPIMDB_MIXED=<0|1>"
 #endif
 
+// this variant's own name for the exponential's coefficient array
+#define PIMDB_CAT2(a, b) a##b
+#define PIMDB_CAT(a, b) PIMDB_CAT2(a, b)
+#define PIMDB_EXP2_SYM PIMDB_CAT(PIMDB_CAT(PIMDB_CAT(exp2_c_j, PIMDB_J), PIMDB_CAT(_b, PIMDB_BOX)), PIMDB_CAT(_m, PIMDB_MIXED))
+
+#include "exchange.h"
+
 namespace pimdb {
 
 template <int J, bool BOX, bool MIXED>
-hipError_t launch_exchange_variant(const LaunchArgs &a, int nitems, int threads, hipStream_t st) {
+hipError_t launch_exchange_variant(const LaunchArgs &a, int nitems, int threads, bool split, hipStream_t st) {
     const size_t smem = exchange_smem_bytes(threads);
     if constexpr (J <= 2) {
-        hipLaunchKernelGGL((k_exchange<J, BOX, MIXED>), dim3(nitems), dim3(threads), smem, st, a);
+        if (split) {
+            if (threads > 512) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_exchange_split<J, BOX, MIXED>), dim3(nitems), dim3(threads), smem, st, a);
+        } else {
+            hipLaunchKernelGGL((k_exchange<J, BOX, MIXED>), dim3(nitems), dim3(threads), smem, st, a);
+        }
     } else {
-        if (threads > 512) return hipErrorInvalidValue;
+        if (threads > 512 || split) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_exchange_wide<J, BOX, MIXED>), dim3(nitems), dim3(threads), smem, st, a);
     }
     return hipGetLastError();
 }
 
+template <int J, bool BOX, bool MIXED>
+int exchange_variant_occupancy(int threads, bool split) {
+    const size_t smem = exchange_smem_bytes(threads);
+    int n = 0;
+    hipError_t e;
+    if constexpr (J <= 2) {
+        if (split)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_exchange_split<J, BOX, MIXED>, threads, smem);
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_exchange<J, BOX, MIXED>, threads, smem);
+    } else {
+        if (split) return 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_exchange_wide<J, BOX, MIXED>, threads, smem);
+    }
+    return e == hipSuccess ? n : 0;
+}
+
 template hipError_t launch_exchange_variant<PIMDB_J, (PIMDB_BOX != 0), (PIMDB_MIXED != 0)>(const LaunchArgs &, int, int,
-                                                                                       hipStream_t);
+                                                                                       bool, hipStream_t);
+template int exchange_variant_occupancy<PIMDB_J, (PIMDB_BOX != 0), (PIMDB_MIXED != 0)>(int, bool);
 
 } // namespace pimdb

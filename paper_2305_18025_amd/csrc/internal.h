@@ -9,9 +9,11 @@ namespace pimdb {
 
 // Roles of a workgroup in the fused evaluation launch.
 enum Role : int32_t {
-    ROLE_FORWARD = 0,  // forward recursion of one system
-    ROLE_BACKWARD = 1, // backward recursion of one system
+    ROLE_FORWARD = 0,  // forward recursion of one system (its serial chain only, when split)
+    ROLE_BACKWARD = 1, // backward recursion of one system (its serial chain only, when split)
     ROLE_SPRINGS = 2,  // interior springs of one block of particles
+    ROLE_FHELP = 3,    // helper of a split forward recursion: accumulators of some blocks
+    ROLE_BHELP = 4,    // helper of a split backward recursion
 };
 
 // Evaluation modes (bit set).
@@ -31,9 +33,10 @@ struct SysDesc {
     int64_t off;    // element offset of the system in packed (P,3,N) arrays
     int64_t ws;     // offset in doubles of the system's region in the workspace
     int64_t st;     // offset in doubles of the system's region in the adjoint state
+    int64_t xs;     // offset in doubles of the split recursions' exchange area (nhelp > 0)
     int32_t N, P;
     int32_t nchunk; // number of ROLE_SPRINGS items (ceil(N / threads))
-    int32_t pad;
+    int32_t nhelp;  // helper workgroups per recursion direction (0: one workgroup per recursion)
     double beta, m, omegaP;
     double k;       // (1/2) m omega_P^2
     double mw2;     // m omega_P^2
@@ -67,6 +70,26 @@ struct WsLayout {
     static __host__ __device__ inline int64_t total(int N, int nchunk) { return cpre(N, nchunk) + N + 1; }
 };
 
+// Exchange area of a split recursion, offsets in doubles from SysDesc::xs
+// (nblk = ceil(N / 64) blocks; direction d = 0 forward, 1 backward):
+//   pub_zl[nblk][64]  step values the chain publishes (what the panels use)
+//   pub_ze[nblk][64]  their exponents (ints)
+//   del_acc[nblk][4][64]  accumulators {A, Wx, Wy, Wz} helpers deliver
+//   del_e[nblk][64]   their exponents (ints)
+// then, for both directions, the flags (ints): [d][0][nblk] block published,
+// [d][1][nblk] accumulator delivered; zero between evaluations (cleared by
+// the finalize launch).
+struct XsLayout {
+    static __host__ __device__ inline int64_t dir(int nblk) { return (int64_t)nblk * 384; }
+    static __host__ __device__ inline int64_t pub_zl(int nblk, int d) { return d * dir(nblk); }
+    static __host__ __device__ inline int64_t pub_ze(int nblk, int d) { return pub_zl(nblk, d) + 64 * (int64_t)nblk; }
+    static __host__ __device__ inline int64_t del_acc(int nblk, int d) { return pub_ze(nblk, d) + 32 * (int64_t)nblk; }
+    static __host__ __device__ inline int64_t del_e(int nblk, int d) { return del_acc(nblk, d) + 256 * (int64_t)nblk; }
+    static __host__ __device__ inline int64_t flags(int nblk) { return 2 * dir(nblk); }
+    static __host__ __device__ inline int64_t nflags(int nblk) { return 4 * (int64_t)nblk; } // ints
+    static __host__ __device__ inline int64_t total(int nblk) { return 2 * dir(nblk) + 2 * (int64_t)nblk; }
+};
+
 // Adjoint state layout per system, offsets in doubles from SysDesc::st:
 //   zf_m[N+1], zf_e[N+1], rf[3][N]
 struct StLayout {
@@ -96,16 +119,25 @@ struct LaunchArgs {
     int32_t mixed;         // 1: FP32 compensated endpoint spring lengths
     int32_t direct;        // 1: direct-form pair lengths for open boundaries (host-side choice of variant)
     int32_t pad;
+    uint64_t wait_ticks;   // time limit of a split recursion's wait, 100 MHz clock ticks
 };
 
 // Kernel launch entry points (kernels.hip).  launch_exchange picks one of
 // the variants compiled from exchange_inst.hip (J accumulator rows per
 // thread, periodic box, mixed precision).
+// `split`: the variant with split recursions (J = 1, 2; 512 threads).
 template <int J, bool BOX, bool MIXED>
-hipError_t launch_exchange_variant(const LaunchArgs &a, int nitems, int threads, hipStream_t st);
-hipError_t launch_exchange(const LaunchArgs &a, int nitems, int threads, int per_thread, hipStream_t st);
+hipError_t launch_exchange_variant(const LaunchArgs &a, int nitems, int threads, bool split, hipStream_t st);
+hipError_t launch_exchange(const LaunchArgs &a, int nitems, int threads, int per_thread, bool split, hipStream_t st);
+// Workgroups of one exchange variant resident per CU at this width (the
+// occupancy the split recursions' waits rely on).
+template <int J, bool BOX, bool MIXED>
+int exchange_variant_occupancy(int threads, bool split);
+int exchange_occupancy(bool box, bool mixed, int threads, int per_thread, bool split);
 hipError_t launch_finalize(const LaunchArgs &a, int S, hipStream_t st);
 hipError_t launch_clear(int32_t *p, int64_t n, hipStream_t st);
+// Zero the split recursions' flags of every split system of the batch.
+hipError_t launch_clear_flags(const LaunchArgs &a, int S, hipStream_t st);
 // Element range of one system handled by one workgroup of the MD kernels.
 struct EChunk {
     int32_t sys;

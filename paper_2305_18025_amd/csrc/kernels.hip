@@ -118,6 +118,22 @@ __device__ __forceinline__ void finalize(const LaunchArgs &a, const SysDesc sd, 
     if (bad) set_flag(a.flags, ST_NONFINITE_OUT);
 }
 
+// The split recursions' flags of one system (one workgroup).
+__device__ __forceinline__ void clear_split_flags(const LaunchArgs &a, const SysDesc &sd) {
+    if (sd.nhelp <= 0) return;
+    const int nblk = (sd.N + 63) / 64;
+    int *fl = (int *)(a.ws + sd.xs + XsLayout::flags(nblk));
+    for (int64_t i = threadIdx.x; i < XsLayout::nflags(nblk); i += blockDim.x) fl[i] = 0;
+}
+
+__global__ void k_clear_flags(LaunchArgs a) { clear_split_flags(a, a.sys[blockIdx.x]); }
+
+hipError_t launch_clear_flags(const LaunchArgs &a, int S, hipStream_t st) {
+    if (S <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_clear_flags, dim3(S), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 // One workgroup per system (memory-latency bound: 512 threads keep twice the
 // loads of 256 in flight; at 1024 the 128-register limit makes it spill).
 constexpr int FIN_T = 512;
@@ -126,6 +142,7 @@ __global__ void __launch_bounds__(FIN_T) k_finalize(LaunchArgs a) {
     __shared__ double red[FIN_T];
     const int si = blockIdx.x;
     SysDesc sd = a.sys[si];
+    clear_split_flags(a, sd); // the next evaluation starts with them at zero
     if (a.offs) {
         sd.off = a.offs[si];
         if (sd.off < 0) return; // flagged by the exchange launch
@@ -144,26 +161,44 @@ hipError_t launch_finalize(const LaunchArgs &a, int S, hipStream_t st) {
 
 // ------------------------------------------------------ exchange dispatch
 template <bool BOX, bool MIXED>
-static hipError_t launch_j(const LaunchArgs &a, int nitems, int threads, int per_thread, hipStream_t st) {
+static int occupancy_j(int threads, int per_thread, bool split) {
     switch (per_thread) {
-    case 1: return launch_exchange_variant<1, BOX, MIXED>(a, nitems, threads, st);
-    case 2: return launch_exchange_variant<2, BOX, MIXED>(a, nitems, threads, st);
-    case 4: return launch_exchange_variant<4, BOX, MIXED>(a, nitems, threads, st);
-    case 8: return launch_exchange_variant<8, BOX, MIXED>(a, nitems, threads, st);
+    case 1: return exchange_variant_occupancy<1, BOX, MIXED>(threads, split);
+    case 2: return exchange_variant_occupancy<2, BOX, MIXED>(threads, split);
+    case 4: return exchange_variant_occupancy<4, BOX, MIXED>(threads, split);
+    case 8: return exchange_variant_occupancy<8, BOX, MIXED>(threads, split);
+    default: return 0;
+    }
+}
+
+int exchange_occupancy(bool box, bool mixed, int threads, int per_thread, bool split) {
+    if (box) return mixed ? occupancy_j<true, true>(threads, per_thread, split)
+                          : occupancy_j<true, false>(threads, per_thread, split);
+    return mixed ? occupancy_j<false, true>(threads, per_thread, split)
+                 : occupancy_j<false, false>(threads, per_thread, split);
+}
+
+template <bool BOX, bool MIXED>
+static hipError_t launch_j(const LaunchArgs &a, int nitems, int threads, int per_thread, bool split, hipStream_t st) {
+    switch (per_thread) {
+    case 1: return launch_exchange_variant<1, BOX, MIXED>(a, nitems, threads, split, st);
+    case 2: return launch_exchange_variant<2, BOX, MIXED>(a, nitems, threads, split, st);
+    case 4: return launch_exchange_variant<4, BOX, MIXED>(a, nitems, threads, split, st);
+    case 8: return launch_exchange_variant<8, BOX, MIXED>(a, nitems, threads, split, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_exchange(const LaunchArgs &a, int nitems, int threads, int per_thread, hipStream_t st) {
+hipError_t launch_exchange(const LaunchArgs &a, int nitems, int threads, int per_thread, bool split, hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
     // the periodic variants with box 0 form every pair displacement directly
     // (the minimum image of d with L = 0 is d exactly): the open FP64 path
     // without the dot-product expansion
     const bool box = a.box > 0 || a.direct;
-    if (box) return a.mixed ? launch_j<true, true>(a, nitems, threads, per_thread, st)
-                            : launch_j<true, false>(a, nitems, threads, per_thread, st);
-    return a.mixed ? launch_j<false, true>(a, nitems, threads, per_thread, st)
-                   : launch_j<false, false>(a, nitems, threads, per_thread, st);
+    if (box) return a.mixed ? launch_j<true, true>(a, nitems, threads, per_thread, split, st)
+                            : launch_j<true, false>(a, nitems, threads, per_thread, split, st);
+    return a.mixed ? launch_j<false, true>(a, nitems, threads, per_thread, split, st)
+                   : launch_j<false, false>(a, nitems, threads, per_thread, split, st);
 }
 
 // ----------------------------------------------------------- small kernels

@@ -133,3 +133,35 @@ def test_graph_survives_retuning():
         torch.cuda.synchronize()
         assert (F1 - F0).abs().max() <= 1e-12 * F0.abs().max()
     assert eng.status() == 0
+
+
+def test_autotune_on_device(tmp_path, monkeypatch):
+    """The launch-shape autotuner times its candidates on the device, applies
+    the fastest, records it in its cache, and a second engine of the same
+    shape takes it from the cache; results stay at the FP64 tolerance."""
+    from paper_2305_18025_amd import tune
+    monkeypatch.setenv(tune.CACHE_ENV, str(tmp_path / "tune.json"))
+    systems = [inputs.System(inputs.cube_system(n, 8, seed=n), beta=1.0) for n in (300, 517, 64)]
+    eng = BosonicExchange([s.N for s in systems], [s.P for s in systems], [s.beta for s in systems],
+                          [s.m for s in systems], [s.omegaP for s in systems])
+    pos = eng.pack([s.R for s in systems])
+    log = []
+    t, p, g, sec = tune.autotune(eng, pos, reps=2, log=log)
+    cands = tune.candidates(max(eng.N), eng.S)
+    assert (t, p, g) in cands and len(log) == len(cands)
+    assert any(x["split"] > 0 for x in log) and any(x["split"] == 0 for x in log)
+    assert eng.split[0] == g and sec == min(x["ms"] for x in log) * 1e-3
+    if g == 0:
+        assert eng.tuning == (t, p)
+    F, E = eng.forces(pos)
+    torch.cuda.synchronize()
+    assert eng.status() == 0
+    for i, s in enumerate(systems):
+        o = _oracle_f80(s)
+        assert abs(float(E[i]) - o["V"]) <= TOL64 * abs(o["V"])
+        assert np.abs(eng.unpack(F, i) - o["F"]).max() <= TOL64 * np.abs(o["F"]).max()
+    eng2 = BosonicExchange([s.N for s in systems], [s.P for s in systems], [s.beta for s in systems],
+                           [s.m for s in systems], [s.omegaP for s in systems])
+    log2 = []
+    assert tune.autotune(eng2, pos, log=log2)[:3] == (t, p, g) and log2 == []
+    assert eng2.split[0] == g

@@ -40,11 +40,12 @@ def _threads():
 def test_open_maximum_size():
     """Open boundaries at the largest N the ABI accepts (4096, exactly 64
     blocks) and a ragged neighbour (4033 = 63 blocks + 1), one batch, the
-    eight-rows-per-thread kernel: unit-density cubes, P = 8."""
+    eight-rows-per-thread kernel (whole recursions; the split form of the
+    same systems is in the split tests): unit-density cubes, P = 8."""
     systems = [inputs.System(inputs.cube_system(4096, 8, seed=21), beta=1.0, name="open N4096"),
                inputs.System(inputs.cube_system(4033, 8, seed=22), beta=1.5, name="open N4033")]
     eng = BosonicExchange([s.N for s in systems], [s.P for s in systems], [s.beta for s in systems],
-                          [s.m for s in systems], [s.omegaP for s in systems])
+                          [s.m for s in systems], [s.omegaP for s in systems], split=0)
     assert eng.tuning[:2] == (512, 8)
     pos = eng.pack([s.R for s in systems])
     F, E = eng.forces(pos)
@@ -54,7 +55,7 @@ def test_open_maximum_size():
         refs = list(ex.map(_oracle_f80, systems))
     E2 = eng.energy(pos)
     mix = BosonicExchange([s.N for s in systems], [s.P for s in systems], [s.beta for s in systems],
-                          [s.m for s in systems], [s.omegaP for s in systems], precision="mixed")
+                          [s.m for s in systems], [s.omegaP for s in systems], precision="mixed", split=0)
     Fm, Em = mix.forces(pos)
     torch.cuda.synchronize()
     assert mix.status() == 0

@@ -5,7 +5,7 @@ import types
 import pytest
 
 from paper_2305_18025_amd import _lib
-from paper_2305_18025_amd.tune import _bucket, cache_key, candidates
+from paper_2305_18025_amd.tune import SPLITS, _bucket, cache_key, candidates
 
 
 def _abi_accepts(threads, per, nmax):
@@ -19,7 +19,12 @@ def test_candidates_are_valid_launch_shapes(nmax):
     c = candidates(nmax)
     assert c, "every supported size has a candidate"
     assert len(set(c)) == len(c)
-    for threads, per in c:
+    whole = [(t, p) for t, p, g in c if g == 0]
+    split = [g for t, p, g in c if g > 0]
+    assert whole, "whole recursions are always a candidate"
+    # split recursions only where a system has blocks beyond its first two
+    assert split == (list(SPLITS) if nmax > 128 else [])
+    for threads, per in whole:
         assert _abi_accepts(threads, per, nmax), (threads, per)
         # no shape that leaves three quarters of the lanes idle, except the
         # narrowest workgroup
@@ -29,8 +34,10 @@ def test_candidates_are_valid_launch_shapes(nmax):
 def test_candidates_up_to_the_largest_system():
     for nmax in range(1, _lib.MAX_N + 1, 37):
         assert candidates(nmax)
-    # above 2048 particles only the 8-rows-per-thread shape holds a system
-    assert candidates(_lib.MAX_N) == [(512, 8)]
+    # above 2048 particles only the 8-rows-per-thread shape holds a whole
+    # recursion; large batches are never split
+    assert candidates(_lib.MAX_N, S=256) == [(512, 8, 0)]
+    assert [g for _, _, g in candidates(_lib.MAX_N, S=1) if g] == list(SPLITS)
 
 
 def test_cache_key_buckets():
