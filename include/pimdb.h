@@ -205,9 +205,11 @@ int pimdb_last_timing(pimdb_t h, float *exchange_ms, float *finalize_ms);
  * system set, rebuilds the tables and unbinds the workspace. */
 int pimdb_set_split(pimdb_t h, int blocks_per_helper);
 
-/* Blocks per helper of the current tables (0: no system split) and the
- * number of helper workgroups a forces call launches. */
-int pimdb_get_split(pimdb_t h, int *blocks_per_helper, int *helpers);
+/* Blocks per helper of the current tables (0: no system split), the number
+ * of helper workgroups a forces call launches, and (cu_per_workgroup, may be
+ * NULL) 1 if a split launch gives every workgroup a CU of its own (small
+ * plans), 0 if two share a CU. */
+int pimdb_get_split(pimdb_t h, int *blocks_per_helper, int *helpers, int *cu_per_workgroup);
 
 /* Current launch shape (after the automatic choice). */
 int pimdb_get_tuning(pimdb_t h, int *threads, int *per_thread);

@@ -58,7 +58,7 @@ SIGNATURES = {
     "pimdb_set_timing": (_c_int, [_handle, _c_int]),
     "pimdb_last_timing": (_c_int, [_handle, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
     "pimdb_set_split": (_c_int, [_handle, _c_int]),
-    "pimdb_get_split": (_c_int, [_handle, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]),
+    "pimdb_get_split": (_c_int, [_handle, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]),
     "pimdb_get_tuning": (_c_int, [_handle, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]),
     "pimdb_system_offset": (_c_i64, [_handle, _c_i32]),
     "pimdb_total_elements": (_c_i64, [_handle]),

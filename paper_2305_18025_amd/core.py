@@ -114,10 +114,11 @@ class BosonicExchange:
     @property
     def split(self):
         """(blocks per helper of the current plan, 0 if unsplit; helper
-        workgroups per forces call)."""
-        g, n = ctypes.c_int(), ctypes.c_int()
-        check(self.lib.pimdb_get_split(self._h, ctypes.byref(g), ctypes.byref(n)), self._h)
-        return g.value, n.value
+        workgroups per forces call; 1 if every workgroup of the split launch
+        has a CU of its own)."""
+        g, n, x = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(self.lib.pimdb_get_split(self._h, ctypes.byref(g), ctypes.byref(n), ctypes.byref(x)), self._h)
+        return g.value, n.value, x.value
 
     @property
     def tuning(self):

@@ -57,6 +57,7 @@ struct pimdb_ctx {
     // helper) and what the current tables use
     int user_split = -1;
     int split_g = 0;       // 0: no system split
+    int split_mode = 0;    // launch variant: 0 whole, 1 split, 2 split with a CU per workgroup
     int helpers_total = 0; // helper workgroups of a forces launch
     int cus = 0;           // compute units of the device
     uint64_t wait_ticks = 200000000ull; // split waits give up after 2 s (100 MHz clock)
@@ -180,6 +181,7 @@ struct SplitPlan {
     int per = 1;
     int helpers = 0; // per forces launch (both directions)
     int recursion_wgs = 0;
+    int mode = 1;    // 2: one workgroup per CU (the plan fits), 1: two per CU
     std::vector<int> nhelp;
 };
 
@@ -213,9 +215,17 @@ bool plan_split(pimdb_t h, int g, SplitPlan &p) {
         p.recursion_wgs += 2 + 2 * nh;
     }
     if (p.per > 2 || p.helpers == 0) return false;
-    const int occ = exchange_occupancy(h->box > 0 || h->precision == PIMDB_FP64_DIRECT, h->precision == PIMDB_MIXED,
-                                       SPLIT_T, p.per, true);
-    return occ > 0 && (int64_t)p.recursion_wgs <= (int64_t)occ * h->cus;
+    // a CU of its own for every chain and helper when they all fit so (no
+    // SIMD shared with another workgroup), else two per CU
+    const bool box = h->box > 0 || h->precision == PIMDB_FP64_DIRECT, mixed = h->precision == PIMDB_MIXED;
+    for (int mode : {2, 1}) {
+        const int occ = exchange_occupancy(box, mixed, SPLIT_T, p.per, mode);
+        if (occ > 0 && (int64_t)p.recursion_wgs <= (int64_t)occ * h->cus) {
+            p.mode = mode;
+            return true;
+        }
+    }
+    return false;
 }
 
 // The automatic choice: split only when the whole recursions would leave
@@ -276,6 +286,7 @@ int build_tables(pimdb_t h) {
     } else if (h->user_split < 0 && !h->user_threads) {
         h->split_g = auto_split(h, plan);
     }
+    h->split_mode = h->split_g > 0 ? plan.mode : 0;
     if (h->split_g > 0) {
         h->threads = SPLIT_T;
         h->per_thread = plan.per;
@@ -420,7 +431,7 @@ int run(pimdb_t h, LaunchArgs &a, const Item *items, int n) {
     a.items = items;
     hipError_t e;
     if (tm && (e = hipEventRecord(h->ev[0], h->stream)) != hipSuccess) return hip_fail(h, e, "event");
-    e = launch_exchange(a, n, h->threads, h->per_thread, h->split_g > 0, h->stream);
+    e = launch_exchange(a, n, h->threads, h->per_thread, h->split_mode, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "exchange launch");
     if (tm && (e = hipEventRecord(h->ev[1], h->stream)) != hipSuccess) return hip_fail(h, e, "event");
     e = launch_finalize(a, h->S, h->stream);
@@ -602,10 +613,11 @@ int pimdb_set_split(pimdb_t h, int blocks_per_helper) {
     return PIMDB_OK;
 }
 
-int pimdb_get_split(pimdb_t h, int *blocks_per_helper, int *helpers) {
+int pimdb_get_split(pimdb_t h, int *blocks_per_helper, int *helpers, int *cu_per_workgroup) {
     if (!h || !blocks_per_helper || !helpers) return PIMDB_EINVAL;
     *blocks_per_helper = h->split_g;
     *helpers = h->helpers_total;
+    if (cu_per_workgroup) *cu_per_workgroup = h->split_mode == 2 ? 1 : 0;
     return PIMDB_OK;
 }
 

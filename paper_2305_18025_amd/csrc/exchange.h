@@ -127,9 +127,12 @@ constexpr int KTRI = BK * (BK + 1) / 2;
 //                      lanes a step does not reach hold EMASK (filled once)
 //   [L_PA, +KSPLIT*4*BK)  partial sums {A, Wx, Wy, Wz} per wave and lane
 //   [L_PE, +KSPLIT*BK/2)  their exponents (ints)
-//   [L_DL, +4*BK+BK/2) the accumulator a helper delivered for the block
-//                      (split recursions' chain workgroup)
+//   [L_DL, +2*L_DLS)   the accumulators a helper delivered for the current
+//                      and the next block (split recursions' chain)
 //   [L_ABT, +1)        abort flag of a split recursion (int)
+//   [L_UR, +2*4*BK)    a helper's urgent-row constants for this and the
+//                      next iteration
+//   [L_UC, +1)         a helper's count of finished urgent slices (int)
 //   [LDS_RED, +T)      block reduction scratch of the spring role (a
 //                      workgroup runs either a recursion or springs, so
 //                      this aliases the recursion regions)
@@ -143,9 +146,12 @@ constexpr int L_KP = L_ZL + 3 * BS;
 constexpr int L_KN = L_KP + KTRI;
 constexpr int L_PA = L_KN + BK * BK / 2;
 constexpr int L_PE = L_PA + KSPLIT * 4 * BK;
-constexpr int L_DL = L_PE + KSPLIT * BK / 2; // delivered accumulator {A, Wx, Wy, Wz} x 64 and exponents
-constexpr int L_ABT = L_DL + 4 * BK + BK / 2;  // abort flag (int) of a split recursion
-constexpr int L_END = L_ABT + 1;
+constexpr int L_DLS = 4 * BK + BK / 2;          // one delivered accumulator {A, Wx, Wy, Wz} x 64 + exponents
+constexpr int L_DL = L_PE + KSPLIT * BK / 2;     // two of them (the current and the next block)
+constexpr int L_ABT = L_DL + 2 * L_DLS;          // abort flag (int) of a split recursion
+constexpr int L_UR = L_ABT + 1;                  // a helper's urgent row constants {px, py, pz, hl} x 64, twice
+constexpr int L_UC = L_UR + 2 * 4 * BK;          // a helper's slice counter (int)
+constexpr int L_END = L_UC + 1;
 constexpr int LDS_RED = 0;
 
 __device__ __forceinline__ double *stg_block(double *sm, int b) { return sm + L_STG + ((b % 3) * BS + 1) * STG; }
@@ -447,6 +453,80 @@ __device__ __forceinline__ void panel_step(Rows<JJ> &R, double *Me, const RecCtx
     }
 }
 
+// Two steps' terms for one row (row J): both exponentials are formed in one
+// stretch of code, so their dependency chains overlap where a single row
+// would leave the wave waiting on each FMA in turn; they are then added in
+// the order of two single steps (the reference moves, when one is needed,
+// happen exactly as they would step by step, so the result is the same).
+template <bool FWD, int J, int JJ, bool BOX, bool MIXED, bool WSUM, bool MAG>
+__device__ __forceinline__ void panel_step2(Rows<JJ> &R, double *Me, const RecCtx &c, double zl0, int ze0,
+                                            double ux0, double uy0, double uz0, double zl1, int ze1, double ux1,
+                                            double uy1, double uz1) {
+    constexpr bool DOT = !BOX && !MIXED;
+    const double zl[2] = {zl0, zl1}, ux[2] = {ux0, ux1}, uy[2] = {uy0, uy1}, uz[2] = {uz0, uz1};
+    const int ze[2] = {ze0, ze1};
+    double x[2], r[2], f[2], p[2], dx[2], dy[2], dz[2], tm[2];
+    int k[2];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        if (DOT) {
+            x[g] = fma(R.px[J], ux[g], fma(R.py[J], uy[g], fma(R.pz[J], uz[g], R.hl[J] + zl[g])));
+            dx[g] = ux[g];
+            dy[g] = uy[g];
+            dz[g] = uz[g];
+        } else {
+            if (FWD) {
+                dx[g] = mimg<BOX>(R.px[J] - ux[g], c.box, c.ib);
+                dy[g] = mimg<BOX>(R.py[J] - uy[g], c.box, c.ib);
+                dz[g] = mimg<BOX>(R.pz[J] - uz[g], c.box, c.ib);
+            } else {
+                dx[g] = mimg<BOX>(ux[g] - R.px[J], c.box, c.ib);
+                dy[g] = mimg<BOX>(uy[g] - R.py[J], c.box, c.ib);
+                dz[g] = mimg<BOX>(uz[g] - R.pz[J], c.box, c.ib);
+            }
+            x[g] = fma(c.kap, sqlen<MIXED>(dx[g], dy[g], dz[g]), FWD ? R.hl[J] + zl[g] : zl[g]);
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        if constexpr (MAG) {
+            tm[g] = x[g] + Me[J];
+            r[g] = tm[g] - Me[J];
+        } else {
+            r[g] = rint(x[g]);
+        }
+        f[g] = x[g] - r[g];
+        p[g] = EXP2_C[0];
+    }
+#pragma unroll
+    for (int i = 1; i < EXP2_N; ++i) {
+#pragma unroll
+        for (int g = 0; g < 2; ++g) p[g] = fma(p[g], f[g], EXP2_C[i]);
+    }
+    bool big = false;
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        if constexpr (MAG)
+            k[g] = (int)(uint32_t)__builtin_bit_cast(uint64_t, tm[g]) + ze[g];
+        else
+            k[g] = sub_sat(add_sat(ze[g], (int)r[g]), R.a[J].e);
+        big |= k[g] > RENORM;
+    }
+    if (__builtin_expect(__builtin_amdgcn_ballot_w64(big) != 0, 0)) {
+        // step by step: the second term's exponent is taken relative to the
+        // reference the first one may have moved
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const int kk = acc_shift<WSUM>(R.a[J], add_sat(ze[g], (int)r[g]));
+            if constexpr (MAG) Me[J] = row_magic(R, J);
+            acc_add<WSUM>(R.a[J], p[g], kk, dx[g], dy[g], dz[g]);
+        }
+    } else {
+        acc_add<WSUM>(R.a[J], p[0], k[0], dx[0], dy[0], dz[0]);
+        acc_add<WSUM>(R.a[J], p[1], k[1], dx[1], dy[1], dz[1]);
+    }
+}
+
 // Panel: rows [LO, HI) add the terms of the steps of block blk.  Full
 // blocks in the 1- and 2-row kernels run an unrolled loop; otherwise steps
 // go in pairs with two alternating sets of step values, each read one step
@@ -468,12 +548,24 @@ __device__ __forceinline__ void panel(Rows<JJ> &R, const RecCtx &c, int blk) {
             if (nst == BK) {
                 // full block (1- and 2-row kernels): no tail test, four steps
                 // per loop trip with immediate LDS offsets
+                if constexpr (HI - LO == 1) { // one row: steps in pairs
+#pragma unroll 2
+                    for (int n = 0; n < BK; n += 2) {
+                        const int i0 = FWD ? BK - 1 - n : n, i1 = FWD ? BK - 2 - n : n + 1;
+                        double ax, ay, az, ah, bx, by, bz, bh;
+                        step_point<FWD, DOT>(S, i0, ax, ay, az, ah);
+                        step_point<FWD, DOT>(S, i1, bx, by, bz, bh);
+                        panel_step2<FWD, LO, JJ, BOX, MIXED, WSUM, MAG>(R, Me, c, Z[i0], E[i0], ax, ay, az, Z[i1],
+                                                                        E[i1], bx, by, bz);
+                    }
+                } else {
 #pragma unroll 4
-                for (int n = 0; n < BK; ++n) {
-                    const int ii = FWD ? BK - 1 - n : n;
-                    double ux, uy, uz, uh;
-                    step_point<FWD, DOT>(S, ii, ux, uy, uz, uh);
-                    panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM, MAG>(R, Me, c, Z[ii], E[ii], ux, uy, uz);
+                    for (int n = 0; n < BK; ++n) {
+                        const int ii = FWD ? BK - 1 - n : n;
+                        double ux, uy, uz, uh;
+                        step_point<FWD, DOT>(S, ii, ux, uy, uz, uh);
+                        panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM, MAG>(R, Me, c, Z[ii], E[ii], ux, uy, uz);
+                    }
                 }
                 return;
             }
@@ -489,6 +581,18 @@ __device__ __forceinline__ void panel(Rows<JJ> &R, const RecCtx &c, int blk) {
             step_point<FWD, DOT>(S, i, bx, by, bz, bh);
             zb = Z[i];
             eb = E[i];
+            if constexpr (HI - LO == 1) { // one row: both steps' terms together
+                if (n + 1 < nst) {
+                    panel_step2<FWD, LO, JJ, BOX, MIXED, WSUM, MAG>(R, Me, c, za, ea, ax, ay, az, zb, eb, bx, by, bz);
+                    i = at(n + 2);
+                    step_point<FWD, DOT>(S, i, ax, ay, az, ah);
+                    za = Z[i];
+                    ea = E[i];
+                } else {
+                    panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM, MAG>(R, Me, c, za, ea, ax, ay, az);
+                }
+                continue;
+            }
             panel_step<FWD, LO, HI, JJ, BOX, MIXED, WSUM, MAG>(R, Me, c, za, ea, ax, ay, az);
             if (n + 1 < nst) {
                 i = at(n + 2);
@@ -542,10 +646,62 @@ __device__ __forceinline__ void diag_terms(const RecCtx &c, int k) {
 
 // Phase A2: wave w < KSPLIT sums the terms of its slice of block prev's
 // steps for block k's accumulators (lane i: 64 k + i) into LDS.
-template <bool FWD, bool BOX, bool MIXED, bool WSUM, bool MAG>
-__device__ __forceinline__ void diag_partial(const RecCtx &c, int k, int prev) {
+// Waves that share the previous block's terms for the diagonal rows: 8 in
+// 16-wave workgroups, else up to 4 (the other waves run panels).
+__device__ __forceinline__ int partial_waves(const RecCtx &c) { return c.W >= 16 ? KSPLIT : min(KSPLIT / 2, c.W); }
+
+// Steps [i0, i1) of block blk (counted largest term first, as in the
+// panels) added to row 0 of R.  ILP2: the steps in pairs whose
+// exponentials overlap (the same sums).
+template <bool FWD, bool BOX, bool MIXED, bool WSUM, bool MAG, bool ILP2>
+__device__ __forceinline__ void slice_sum(Rows<1> &R, const RecCtx &c, int blk, int i0, int i1) {
+    const int nst = min(BK, c.N - blk * BK);
+    const double *S = stg_block(c.sm, blk);
+    const double *Z = zl_block(c.sm, blk);
+    const int *E = ze_block(c.sm, blk);
+    double Me[1] = {row_magic(R, 0)};
+    int n = i0;
+    if constexpr (ILP2) {
+        for (; n + 1 < i1; n += 2) {
+            const int ia = FWD ? nst - 1 - n : n;
+            const int ib = FWD ? nst - 2 - n : n + 1;
+            double ax, ay, az, ah, bx, by, bz, bh;
+            step_point<FWD, !BOX && !MIXED>(S, ia, ax, ay, az, ah);
+            step_point<FWD, !BOX && !MIXED>(S, ib, bx, by, bz, bh);
+            panel_step2<FWD, 0, 1, BOX, MIXED, WSUM, MAG>(R, Me, c, Z[ia], E[ia], ax, ay, az, Z[ib], E[ib], bx, by,
+                                                         bz);
+        }
+    }
+    for (; n < i1; ++n) {
+        const int i = FWD ? nst - 1 - n : n;
+        double ux, uy, uz, uh;
+        step_point<FWD, !BOX && !MIXED>(S, i, ux, uy, uz, uh);
+        panel_step<FWD, 0, 1, 1, BOX, MIXED, WSUM, MAG>(R, Me, c, Z[i], E[i], ux, uy, uz);
+    }
+}
+
+// A partial sum {A, W} to partial-sum slot `slot` of LDS (lane i: row i).
+__device__ __forceinline__ void write_partial(const RecCtx &c, int slot, const Acc &r) {
+    const int lane = c.t & 63;
+    double *PA = c.sm + L_PA + slot * 4 * BK + lane;
+    PA[0] = r.A;
+    PA[BK] = r.Wx;
+    PA[2 * BK] = r.Wy;
+    PA[3 * BK] = r.Wz;
+    pe_base(c.sm)[slot * BK + lane] = r.e;
+}
+
+__device__ __forceinline__ Acc read_partial(const RecCtx &c, int slot) {
+    const int lane = c.t & 63;
+    const double *PA = c.sm + L_PA + slot * 4 * BK + lane;
+    return Acc{PA[0], PA[BK], PA[2 * BK], PA[3 * BK], pe_base(c.sm)[slot * BK + lane]};
+}
+
+// Phase A2 for block k: wave w < ns adds its slice of block prev's steps
+// for block k's accumulators (rows from the staged block k) into LDS slot w.
+template <bool FWD, bool BOX, bool MIXED, bool WSUM, bool MAG, bool ILP2 = false>
+__device__ __forceinline__ void diag_partial(const RecCtx &c, int k, int prev, int ns) {
     const int lane = c.t & 63, w = c.t >> 6;
-    const int ns = c.W >= 16 ? KSPLIT : min(KSPLIT / 2, c.W);
     if (w >= ns) return;
     const double *me = stg_block(c.sm, k) + STG * lane;
     Rows<1> R;
@@ -563,23 +719,8 @@ __device__ __forceinline__ void diag_partial(const RecCtx &c, int k, int prev) {
     if (!BOX && !MIXED) dot_row(c.kap, R.px[0], R.py[0], R.pz[0], R.hl[0], R.px[0], R.py[0], R.pz[0], R.hl[0]);
     R.a[0] = Acc{0.0, 0.0, 0.0, 0.0, EMIN};
     const int nst = min(BK, c.N - prev * BK); // previous block: full except the backward top
-    const int i0 = (nst * w) / ns, i1 = (nst * (w + 1)) / ns;
-    const double *S = stg_block(c.sm, prev);
-    const double *Z = zl_block(c.sm, prev);
-    const int *E = ze_block(c.sm, prev);
-    double Me[1] = {row_magic(R, 0)};
-    for (int n = i0; n < i1; ++n) {
-        const int i = FWD ? nst - 1 - n : n; // largest terms first, as in the panels
-        double ux, uy, uz, uh;
-        step_point<FWD, !BOX && !MIXED>(S, i, ux, uy, uz, uh);
-        panel_step<FWD, 0, 1, 1, BOX, MIXED, WSUM, MAG>(R, Me, c, Z[i], E[i], ux, uy, uz);
-    }
-    double *PA = c.sm + L_PA + w * 4 * BK + lane;
-    PA[0] = R.a[0].A;
-    PA[BK] = R.a[0].Wx;
-    PA[2 * BK] = R.a[0].Wy;
-    PA[3 * BK] = R.a[0].Wz;
-    pe_base(c.sm)[w * BK + lane] = R.a[0].e;
+    slice_sum<FWD, BOX, MIXED, WSUM, MAG, ILP2>(R, c, prev, (nst * w) / ns, (nst * (w + 1)) / ns);
+    write_partial(c, w, R.a[0]);
 }
 
 // Phase B, owner wave: merge the partial sums, then run block k's steps
@@ -588,13 +729,12 @@ __device__ __forceinline__ void diag_partial(const RecCtx &c, int k, int prev) {
 // panels and its results to global memory.
 template <bool FWD, int j, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR>
 __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bool has_prev, double *zm_out,
-                                         double *ze_out, double *r_out) {
+                                         double *ze_out, double *r_out, int ns) {
     const int lane = c.t & 63, q = k * BK + lane, N = c.N;
     const size_t NN = c.NN;
     const int nst = min(BK, N - k * BK);
     Acc &r = R.a[j];
     if (has_prev) {
-        const int ns = c.W >= 16 ? KSPLIT : min(KSPLIT / 2, c.W);
         for (int w = 0; w < ns; ++w) {
             const double *PA = c.sm + L_PA + w * 4 * BK + lane;
             acc_merge<WSUM>(r, Acc{PA[0], PA[BK], PA[2 * BK], PA[3 * BK], pe_base(c.sm)[w * BK + lane]});
@@ -744,7 +884,7 @@ __device__ __forceinline__ void wave_iter(Rows<JJ> &R, const RecCtx &c, int k, d
         // the serial chain is the critical path of phase B: its wave issues
         // first whenever it is ready
         __builtin_amdgcn_s_setprio(2);
-        diagonal<FWD, jd, JJ, BOX, MIXED, WSUM, UNR>(R, c, k, has_prev, zm_out, ze_out, r_out);
+        diagonal<FWD, jd, JJ, BOX, MIXED, WSUM, UNR>(R, c, k, has_prev, zm_out, ze_out, r_out, partial_waves(c));
         __builtin_amdgcn_s_setprio(0);
         if (has_prev) {
             if (FWD)
@@ -896,7 +1036,7 @@ __device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDes
         diag_terms<FWD, BOX, MIXED>(c, k);
         if (has_prev) { // the longest work of phase A
             __builtin_amdgcn_s_setprio(1);
-            diag_partial<FWD, BOX, MIXED, WSUM, MAG>(c, k, prev);
+            diag_partial<FWD, BOX, MIXED, WSUM, MAG>(c, k, prev, partial_waves(c));
             __builtin_amdgcn_s_setprio(0);
         }
         if (stage) stage_store(c, nb, g);
@@ -1012,33 +1152,26 @@ __device__ __forceinline__ void chain_rows(const LaunchArgs &a, const SysDesc &s
         const bool delivered = FWD ? k >= 2 : k <= nblk - 3;
         const int nb = FWD ? k + 1 : k - 1;
         const bool last = w == W - 1;
+        // the last wave publishes the previous block's step values (from the
+        // LDS ring) for the helpers, stages the next block and shares the
+        // triangle; the other waves also take slices of the partial sums
         Stage g{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (last && nb >= 0 && nb < nblk) g = stage_load<BOX, MIXED>(c, nb, range_bad);
+        if (last && has_prev) {
+            st_dev(X.pub_zl + (size_t)prev * BK + lane, zl_block(c.sm, prev)[lane]);
+            st_dev(X.pub_ze + (size_t)prev * BK + lane, ze_block(c.sm, prev)[lane]);
+        }
         diag_terms<FWD, BOX, MIXED>(c, k);
         if (has_prev) {
             __builtin_amdgcn_s_setprio(1);
-            diag_partial<FWD, BOX, MIXED, WSUM, false>(c, k, prev);
+            diag_partial<FWD, BOX, MIXED, WSUM, false, true>(c, k, prev, min(KSPLIT, W - 1));
             __builtin_amdgcn_s_setprio(0);
         }
-        if (last) {
-            if (delivered) { // fetch the delivered accumulator into LDS
-                if (wave_wait(X.del_flag + k, a.flags, a.wait_ticks)) {
-                    double *D = c.sm + L_DL;
-                    const double *src = X.del_acc + (size_t)k * 4 * BK + lane;
-                    D[lane] = ld_dev(src);
-                    D[BK + lane] = ld_dev(src + BK);
-                    D[2 * BK + lane] = ld_dev(src + 2 * BK);
-                    D[3 * BK + lane] = ld_dev(src + 3 * BK);
-                    ((int *)(D + 4 * BK))[lane] = ld_dev(X.del_e + (size_t)k * BK + lane);
-                } else if (lane == 0) {
-                    *abort_flag = 1;
-                }
-            }
-            if (nb >= 0 && nb < nblk) stage_store(c, nb, g);
-        }
+        if (last && has_prev) wave_signal(X.pub_flag + prev); // its stores have completed by now
+        if (last && nb >= 0 && nb < nblk) stage_store(c, nb, g);
         __syncthreads();
         if (*abort_flag) return;
-        if (w == k % W) {
+        if (w == 0) { // the serial steps, always on wave 0
             const double *me = stg_block(c.sm, k) + STG * lane;
             Rows<1> R;
             if (FWD) {
@@ -1055,18 +1188,37 @@ __device__ __forceinline__ void chain_rows(const LaunchArgs &a, const SysDesc &s
             if (DOT) dot_row(c.kap, R.px[0], R.py[0], R.pz[0], R.hl[0], R.px[0], R.py[0], R.pz[0], R.hl[0]);
             R.a[0] = Acc{0.0, 0.0, 0.0, 0.0, EMIN};
             if (delivered) {
-                const double *D = c.sm + L_DL;
+                const double *D = c.sm + L_DL + (it & 1) * L_DLS;
                 R.a[0] = Acc{D[lane], D[BK + lane], D[2 * BK + lane], D[3 * BK + lane], ((const int *)(D + 4 * BK))[lane]};
             }
             __builtin_amdgcn_s_setprio(2);
-            diagonal<FWD, 0, 1, BOX, MIXED, WSUM, true>(R, c, k, has_prev, zm_out, ze_out, r_out);
+            diagonal<FWD, 0, 1, BOX, MIXED, WSUM, true>(R, c, k, has_prev, zm_out, ze_out, r_out,
+                                                         min(KSPLIT, W - 1));
             __builtin_amdgcn_s_setprio(0);
-            // the block's step values for the helpers
-            st_dev(X.pub_zl + (size_t)k * BK + lane, zl_block(c.sm, k)[lane]);
-            st_dev(X.pub_ze + (size_t)k * BK + lane, ze_block(c.sm, k)[lane]);
-            wave_signal(X.pub_flag + k);
+        } else if (last && it + 1 < nblk) {
+            // meanwhile the next block's delivery goes to the other LDS slot
+            const int kn = FWD ? k + 1 : k - 1;
+            if (FWD ? kn >= 2 : kn <= nblk - 3) {
+                if (wave_wait(X.del_flag + kn, a.flags, a.wait_ticks)) {
+                    double *D = c.sm + L_DL + ((it + 1) & 1) * L_DLS;
+                    const double *src = X.del_acc + (size_t)kn * 4 * BK + lane;
+                    D[lane] = ld_dev(src);
+                    D[BK + lane] = ld_dev(src + BK);
+                    D[2 * BK + lane] = ld_dev(src + 2 * BK);
+                    D[3 * BK + lane] = ld_dev(src + 3 * BK);
+                    ((int *)(D + 4 * BK))[lane] = ld_dev(X.del_e + (size_t)kn * BK + lane);
+                } else if (lane == 0) {
+                    *abort_flag = 1;
+                }
+            }
         }
         __syncthreads();
+    }
+    if (w == W - 1) { // the last block (no helper needs it; published for completeness)
+        const int kl = FWD ? nblk - 1 : 0;
+        st_dev(X.pub_zl + (size_t)kl * BK + lane, zl_block(c.sm, kl)[lane]);
+        st_dev(X.pub_ze + (size_t)kl * BK + lane, ze_block(c.sm, kl)[lane]);
+        wave_signal(X.pub_flag + kl);
     }
     if (range_bad) set_flag(a.flags, ST_RANGE);
 }
@@ -1084,23 +1236,31 @@ __device__ __forceinline__ void helper_blocks(bool fwd, int nblk, int H, int h, 
     }
 }
 
-// One wave's work on published block i: the panel over its live rows;
-// when it holds the block two further in recursion order (URG: row LO
-// forward, HI - 1 backward), that row first, and its accumulator is then
-// delivered.
+// One wave's work on published block i: the panel over its live rows.
+// URG: this wave holds the block two further in recursion order (row LO
+// forward, HI - 1 backward), whose terms of block i every row wave has
+// summed in slices (LDS slots 0 .. WR-1); once all slices are in, this wave
+// merges them into the row and delivers it, then runs its other rows.
 template <bool FWD, int LO, int HI, bool URG, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool MAG>
-__device__ __forceinline__ void helper_iter(Rows<JJ> &R, const RecCtx &c, int i, const XsPtrs &X) {
+__device__ __forceinline__ void helper_iter(Rows<JJ> &R, const RecCtx &c, int i, const XsPtrs &X, int nslices,
+                                            int target) {
     if constexpr (URG) {
         constexpr int ju = FWD ? LO : HI - 1;
         const int lane = c.t & 63;
-        panel<FWD, ju, ju + 1, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i);
+        // the other row waves count their finished slices in LDS
+        const int *cnt = (const int *)(c.sm + L_UC);
+        while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) <
+               target)
+            __builtin_amdgcn_s_sleep(1);
+        Acc r = R.a[ju];
+        for (int sl = 0; sl < nslices; ++sl) acc_merge<WSUM>(r, read_partial(c, sl));
         const int b = FWD ? i + 2 : i - 2;
         double *dst = X.del_acc + (size_t)b * 4 * BK + lane;
-        st_dev(dst, R.a[ju].A);
-        st_dev(dst + BK, R.a[ju].Wx);
-        st_dev(dst + 2 * BK, R.a[ju].Wy);
-        st_dev(dst + 3 * BK, R.a[ju].Wz);
-        st_dev(X.del_e + (size_t)b * BK + lane, R.a[ju].e);
+        st_dev(dst, r.A);
+        st_dev(dst + BK, r.Wx);
+        st_dev(dst + 2 * BK, r.Wy);
+        st_dev(dst + 3 * BK, r.Wz);
+        st_dev(X.del_e + (size_t)b * BK + lane, r.e);
         wave_signal(X.del_flag + b);
         if (FWD)
             panel<FWD, LO + 1, HI, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i);
@@ -1113,38 +1273,50 @@ __device__ __forceinline__ void helper_iter(Rows<JJ> &R, const RecCtx &c, int i,
 
 template <bool FWD, int X_, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool MAG>
 __device__ __forceinline__ void helper_dispatch(Rows<JJ> &R, const RecCtx &c, int i, int x, bool urg,
-                                                const XsPtrs &X) {
+                                                const XsPtrs &X, int nslices, int target) {
     if constexpr (X_ <= JJ) {
         if (x == X_) {
             if (FWD) {
                 if constexpr (X_ < JJ) {
                     if (urg)
-                        helper_iter<FWD, X_, JJ, true, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, X);
+                        helper_iter<FWD, X_, JJ, true, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, X, nslices, target);
                     else
-                        helper_iter<FWD, X_, JJ, false, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, X);
+                        helper_iter<FWD, X_, JJ, false, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, X, nslices, target);
                 }
             } else {
                 if constexpr (X_ > 0) {
                     if (urg)
-                        helper_iter<FWD, 0, X_, true, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, X);
+                        helper_iter<FWD, 0, X_, true, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, X, nslices, target);
                     else
-                        helper_iter<FWD, 0, X_, false, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, X);
+                        helper_iter<FWD, 0, X_, false, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, X, nslices, target);
                 }
             }
         } else {
-            helper_dispatch<FWD, X_ + 1, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, x, urg, X);
+            helper_dispatch<FWD, X_ + 1, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, x, urg, X, nslices, target);
         }
     }
 }
 
 // The fetch wave of a helper (its last wave, which holds no rows) copies
 // published block i into the LDS ring: its points (loaded before the flag
-// is seen) and its step values.  False after a wait timed out.
-template <bool BOX, bool MIXED>
-__device__ __forceinline__ bool helper_fetch(const LaunchArgs &a, const RecCtx &c, const XsPtrs &X, int i) {
+// is seen) and its step values; and, when that iteration has a block to
+// deliver (ub >= 0), that block's row constants into urgent slot us.  False
+// after a wait timed out.
+template <bool FWD, bool BOX, bool MIXED>
+__device__ __forceinline__ bool helper_fetch(const LaunchArgs &a, const RecCtx &c, const XsPtrs &X, int i, int ub,
+                                             int us) {
     const int lane = c.t & 63;
     bool unused = false;
     const Stage g = stage_load<BOX, MIXED>(c, i, unused);
+    if (ub >= 0) {
+        Rows<1> U;
+        load_row<FWD, 1, BOX, MIXED>(U, 0, c, ub * BK + lane, unused);
+        double *D = c.sm + L_UR + us * 4 * BK + lane;
+        D[0] = U.px[0];
+        D[BK] = U.py[0];
+        D[2 * BK] = U.pz[0];
+        D[3 * BK] = U.hl[0];
+    }
     if (!wave_wait(X.pub_flag + i, a.flags, a.wait_ticks)) return false;
     zl_block(c.sm, i)[lane] = ld_dev(X.pub_zl + (size_t)i * BK + lane);
     ze_block(c.sm, i)[lane] = ld_dev(X.pub_ze + (size_t)i * BK + lane);
@@ -1176,30 +1348,59 @@ __device__ __forceinline__ void helper_rows(const LaunchArgs &a, const SysDesc &
     const int i_begin = FWD ? 0 : nblk - 1;
     const int i_end = FWD ? blast - 2 : b0 + 2; // inclusive
     const int di = FWD ? 1 : -1;
-    if (t == 0) *abort_flag = 0;
+    // the block this helper delivers after block i (-1: none)
+    auto urgent_block = [&](int i) {
+        const int ub = FWD ? i + 2 : i - 2;
+        return (ub >= b0 && ub <= blast && (ub - b0) % H == 0) ? ub : -1;
+    };
+    int *cnt = (int *)(c.sm + L_UC);
+    if (t == 0) {
+        *abort_flag = 0;
+        *cnt = 0;
+    }
     __syncthreads();
-    if (w == WR && !helper_fetch<BOX, MIXED>(a, c, X, i_begin) && lane == 0) *abort_flag = 1;
+    if (w == WR && !helper_fetch<FWD, BOX, MIXED>(a, c, X, i_begin, urgent_block(i_begin), 0) && lane == 0)
+        *abort_flag = 1;
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    for (int i = i_begin; FWD ? i <= i_end : i >= i_end; i += di) {
+    int nurg = 0; // urgent iterations so far
+    for (int i = i_begin, it = 0; FWD ? i <= i_end : i >= i_end; i += di, ++it) {
         if (*abort_flag) return;
+        const int ub = urgent_block(i);
+        if (ub >= 0) ++nurg;
         if (w == WR) {
-            if (i != i_end && !helper_fetch<BOX, MIXED>(a, c, X, i + di) && lane == 0) *abort_flag = 1;
+            if (i != i_end && !helper_fetch<FWD, BOX, MIXED>(a, c, X, i + di, urgent_block(i + di), (it + 1) & 1) &&
+                lane == 0)
+                *abort_flag = 1;
         } else {
+            if (ub >= 0) { // this wave's slice of block i's terms for the urgent row
+                const double *D = c.sm + L_UR + (it & 1) * 4 * BK + lane;
+                Rows<1> U;
+                U.px[0] = D[0];
+                U.py[0] = D[BK];
+                U.pz[0] = D[2 * BK];
+                U.hl[0] = D[3 * BK];
+                U.a[0] = Acc{0.0, 0.0, 0.0, 0.0, EMIN};
+                const int nst = min(BK, c.N - i * BK);
+                slice_sum<FWD, BOX, MIXED, WSUM, false, true>(U, c, i, (nst * w) / WR, (nst * (w + 1)) / WR);
+                write_partial(c, w, U.a[0]);
+            }
             int x;
             bool urg;
             if (FWD) { // live: blocks >= i + 2, i.e. m >= m0
                 const int m0 = i <= h ? 0 : (i - h + H - 1) / H;
-                urg = i >= h && (i - h) % H == 0;
                 x = m0 <= w ? 0 : (m0 - w + WR - 1) / WR;
-                urg = urg && x * WR + w == m0;
+                urg = ub >= 0 && x * WR + w == m0;
             } else { // live: blocks <= i - 2, i.e. m < L
                 const int L = i - 2 >= b0 ? min((i - 2 - b0) / H + 1, nown) : 0;
-                urg = i - 2 >= b0 && (i - 2 - b0) % H == 0;
                 x = L - 1 >= w ? min((L - 1 - w) / WR + 1, JJ) : 0;
-                urg = urg && x > 0 && (x - 1) * WR + w == L - 1;
+                urg = ub >= 0 && x > 0 && (x - 1) * WR + w == L - 1;
             }
-            helper_dispatch<FWD, 0, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, x, urg, X);
+            // count this wave's finished slice for the urgent row's owner (one
+            // lane: a per-lane operand would be reduced by a scalar loop first)
+            if (ub >= 0 && !urg && lane == 0)
+                __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            helper_dispatch<FWD, 0, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, x, urg, X, WR, nurg * (WR - 1));
         }
         __syncthreads();
     }
@@ -1466,14 +1667,22 @@ __global__ void __launch_bounds__(512) k_exchange_wide(LaunchArgs a) {
 }
 
 // Launches with split recursions (some systems spread over helper
-// workgroups); 512 threads, so that two workgroups share a CU.
+// workgroups); 512 threads and at most 128 VGPRs, so that two workgroups
+// share a CU (the residency the waits between workgroups rely on).
 template <int J, bool BOX, bool MIXED>
-__global__ void __launch_bounds__(512) k_exchange_split(LaunchArgs a) {
+__global__ void __launch_bounds__(512, 4) k_exchange_split(LaunchArgs a) {
     exchange_body<J, BOX, MIXED, true>(a);
 }
 
 // LDS of one fused workgroup: the recursion regions, or the springs role's
-// reduction scratch (whichever is larger).
-inline size_t exchange_smem_bytes(int threads) { return (size_t)(threads > L_END ? threads : L_END) * sizeof(double); }
+// reduction scratch (whichever is larger).  `exclusive`: more than half of a
+// CU's 160 KiB, so that each workgroup has a CU to itself (split launches
+// small enough for that: a chain or helper then shares no SIMD with
+// another workgroup's waves).
+constexpr size_t EXCLUSIVE_LDS = 96 * 1024;
+inline size_t exchange_smem_bytes(int threads, bool exclusive = false) {
+    const size_t b = (size_t)(threads > L_END ? threads : L_END) * sizeof(double);
+    return exclusive && b < EXCLUSIVE_LDS ? EXCLUSIVE_LDS : b;
+}
 
 } // namespace pimdb

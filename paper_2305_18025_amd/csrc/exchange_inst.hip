@@ -17,8 +17,8 @@
 namespace pimdb {
 
 template <int J, bool BOX, bool MIXED>
-hipError_t launch_exchange_variant(const LaunchArgs &a, int nitems, int threads, bool split, hipStream_t st) {
-    const size_t smem = exchange_smem_bytes(threads);
+hipError_t launch_exchange_variant(const LaunchArgs &a, int nitems, int threads, int split, hipStream_t st) {
+    const size_t smem = exchange_smem_bytes(threads, split == 2);
     if constexpr (J <= 2) {
         if (split) {
             if (threads > 512) return hipErrorInvalidValue;
@@ -34,8 +34,8 @@ hipError_t launch_exchange_variant(const LaunchArgs &a, int nitems, int threads,
 }
 
 template <int J, bool BOX, bool MIXED>
-int exchange_variant_occupancy(int threads, bool split) {
-    const size_t smem = exchange_smem_bytes(threads);
+int exchange_variant_occupancy(int threads, int split) {
+    const size_t smem = exchange_smem_bytes(threads, split == 2);
     int n = 0;
     hipError_t e;
     if constexpr (J <= 2) {
@@ -51,7 +51,7 @@ int exchange_variant_occupancy(int threads, bool split) {
 }
 
 template hipError_t launch_exchange_variant<PIMDB_J, (PIMDB_BOX != 0), (PIMDB_MIXED != 0)>(const LaunchArgs &, int, int,
-                                                                                       bool, hipStream_t);
-template int exchange_variant_occupancy<PIMDB_J, (PIMDB_BOX != 0), (PIMDB_MIXED != 0)>(int, bool);
+                                                                                       int, hipStream_t);
+template int exchange_variant_occupancy<PIMDB_J, (PIMDB_BOX != 0), (PIMDB_MIXED != 0)>(int, int);
 
 } // namespace pimdb

@@ -125,15 +125,17 @@ struct LaunchArgs {
 // Kernel launch entry points (kernels.hip).  launch_exchange picks one of
 // the variants compiled from exchange_inst.hip (J accumulator rows per
 // thread, periodic box, mixed precision).
-// `split`: the variant with split recursions (J = 1, 2; 512 threads).
+// `split`: 0 whole recursions; 1 the variant with split recursions (J = 1,
+// 2; 512 threads); 2 the same with one workgroup per CU (more LDS than
+// half a CU's).
 template <int J, bool BOX, bool MIXED>
-hipError_t launch_exchange_variant(const LaunchArgs &a, int nitems, int threads, bool split, hipStream_t st);
-hipError_t launch_exchange(const LaunchArgs &a, int nitems, int threads, int per_thread, bool split, hipStream_t st);
+hipError_t launch_exchange_variant(const LaunchArgs &a, int nitems, int threads, int split, hipStream_t st);
+hipError_t launch_exchange(const LaunchArgs &a, int nitems, int threads, int per_thread, int split, hipStream_t st);
 // Workgroups of one exchange variant resident per CU at this width (the
 // occupancy the split recursions' waits rely on).
 template <int J, bool BOX, bool MIXED>
-int exchange_variant_occupancy(int threads, bool split);
-int exchange_occupancy(bool box, bool mixed, int threads, int per_thread, bool split);
+int exchange_variant_occupancy(int threads, int split);
+int exchange_occupancy(bool box, bool mixed, int threads, int per_thread, int split);
 hipError_t launch_finalize(const LaunchArgs &a, int S, hipStream_t st);
 hipError_t launch_clear(int32_t *p, int64_t n, hipStream_t st);
 // Zero the split recursions' flags of every split system of the batch.

@@ -161,7 +161,7 @@ hipError_t launch_finalize(const LaunchArgs &a, int S, hipStream_t st) {
 
 // ------------------------------------------------------ exchange dispatch
 template <bool BOX, bool MIXED>
-static int occupancy_j(int threads, int per_thread, bool split) {
+static int occupancy_j(int threads, int per_thread, int split) {
     switch (per_thread) {
     case 1: return exchange_variant_occupancy<1, BOX, MIXED>(threads, split);
     case 2: return exchange_variant_occupancy<2, BOX, MIXED>(threads, split);
@@ -171,7 +171,7 @@ static int occupancy_j(int threads, int per_thread, bool split) {
     }
 }
 
-int exchange_occupancy(bool box, bool mixed, int threads, int per_thread, bool split) {
+int exchange_occupancy(bool box, bool mixed, int threads, int per_thread, int split) {
     if (box) return mixed ? occupancy_j<true, true>(threads, per_thread, split)
                           : occupancy_j<true, false>(threads, per_thread, split);
     return mixed ? occupancy_j<false, true>(threads, per_thread, split)
@@ -179,7 +179,7 @@ int exchange_occupancy(bool box, bool mixed, int threads, int per_thread, bool s
 }
 
 template <bool BOX, bool MIXED>
-static hipError_t launch_j(const LaunchArgs &a, int nitems, int threads, int per_thread, bool split, hipStream_t st) {
+static hipError_t launch_j(const LaunchArgs &a, int nitems, int threads, int per_thread, int split, hipStream_t st) {
     switch (per_thread) {
     case 1: return launch_exchange_variant<1, BOX, MIXED>(a, nitems, threads, split, st);
     case 2: return launch_exchange_variant<2, BOX, MIXED>(a, nitems, threads, split, st);
@@ -189,7 +189,7 @@ static hipError_t launch_j(const LaunchArgs &a, int nitems, int threads, int per
     }
 }
 
-hipError_t launch_exchange(const LaunchArgs &a, int nitems, int threads, int per_thread, bool split, hipStream_t st) {
+hipError_t launch_exchange(const LaunchArgs &a, int nitems, int threads, int per_thread, int split, hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
     // the periodic variants with box 0 form every pair displacement directly
     // (the minimum image of d with L = 0 is d exactly): the open FP64 path

@@ -43,11 +43,10 @@ def _assert_parity(eng, F, E, systems, tol):
 
 
 @pytest.mark.parametrize("g", [1, 3, 7, 14])
-def test_split_equals_whole_bitwise(g):
+def test_split_equals_whole(g):
     """Systems of 129 (one helper block), 300, 1024 and 2049 particles (a
     ragged last block) in one batch: the split launch with g blocks per
-    helper returns exactly the numbers of the whole recursions at the same
-    workgroup width (same terms, same order, same partial-sum slices)."""
+    helper agrees with the whole recursions to rounding."""
     systems = [System(cube_system(n, 8, seed=n), beta=b, name="N%d" % n)
                for n, b in [(129, 1.0), (300, 0.7), (1024, 1.0), (2049, 1.3)]]
     sp, pos = _engine(systems, split=g)
@@ -62,9 +61,11 @@ def test_split_equals_whole_bitwise(g):
     print("g=%d: %d helpers, %d rows per thread" % (g, sp.split[1], per))
     if g == 7:
         _assert_parity(sp, F1, E1, systems, TOL64)
-    # the whole-recursion reference at 512 threads with 8 rows (same slices)
-    assert torch.equal(E1, E0)
-    assert torch.equal(F1, F0)
+    # the whole-recursion reference at 512 threads with 8 rows: the same
+    # terms, summed in slightly different slices (the split chain shares
+    # the previous block's terms among all its waves)
+    assert ((E1 - E0).abs() <= 1e-14 * E0.abs()).all()
+    assert (F1 - F0).abs().max() <= 1e-13 * F0.abs().max()
 
 
 def test_split_plain_headline_automatic():
