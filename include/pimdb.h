@@ -83,6 +83,17 @@ extern "C" {
                                it still assures 1e-10 it sets PIMDB_STATUS_PRECISION.  This mode
                                has no such bound (about 25% slower). */
 
+/* ---- algorithms (pimdb_set_algorithm) ---- */
+#define PIMDB_ALG_FAST 0     /* the quadratic algorithm (Alg. 1, "Fast PIMD-B"); default */
+#define PIMDB_ALG_ORIGINAL 1 /* the original cubic algorithm (appendix "Algorithm Pseudocode", the
+                                original method; Background): a comparison path, FP64 only */
+/* shift of the forward recurrence's exponential sums under PIMDB_ALG_ORIGINAL
+ * (appendix "Numerical Stability"; any shift is exact in exact arithmetic) */
+#define PIMDB_SHIFT_MIN 0      /* the smallest exponent of each sum (largest term 1); default */
+#define PIMDB_SHIFT_TWO_TERM 1 /* the smaller of E^[1,v] and V^[1,v-1] + E^[v,v]: overflows
+                                  (PIMDB_STATUS_NONFINITE_OUTPUT) once another term lies more than
+                                  about 709/beta below both */
+
 /* ---- device status bits (pimdb_status) ---- */
 #define PIMDB_STATUS_NONFINITE_INPUT 1  /* a position was NaN or infinite */
 #define PIMDB_STATUS_NONFINITE_OUTPUT 2 /* an energy or force came out NaN or infinite */
@@ -169,6 +180,25 @@ int pimdb_set_trap(pimdb_t h, double w);
 /* PIMDB_FP64 (default), PIMDB_MIXED or PIMDB_FP64_DIRECT; PIMDB_EINVAL
  * otherwise.  Takes effect at the next evaluation call. */
 int pimdb_set_precision(pimdb_t h, int mode);
+
+/* Select the algorithm of pimdb_exchange_forces, pimdb_exchange_energy and
+ * pimdb_md_step.  PIMDB_ALG_ORIGINAL evaluates the original method of the
+ * appendix "Algorithm Pseudocode" (Background, "cubic scaling bosonic
+ * PIMD"): cycle energies from their defining sum, the forward recurrence
+ * with the chosen shift, and the forces from the derivative of that
+ * recurrence evaluated for every bead coordinate, O(P N^3) time and
+ * O(P N^2) workspace doubles per system (about 0.8 GB at N = 1024, P = 32);
+ * it always computes in FP64 (the precision mode is ignored), honours the
+ * box and the trap, and gives the same potential and forces as
+ * PIMDB_ALG_FAST to rounding.  shift must be PIMDB_SHIFT_MIN with
+ * PIMDB_ALG_FAST.  With a system set, this rebuilds the tables and unbinds
+ * the workspace like pimdb_set_batch.  Under PIMDB_ALG_ORIGINAL the batched,
+ * static-scratch, energy-save and adjoint entries return PIMDB_EINVAL, and
+ * pimdb_debug_get still exports the quadratic algorithm's tables.
+ * PIMDB_EINVAL for unknown values. */
+int pimdb_set_algorithm(pimdb_t h, int algorithm, int shift);
+/* The current algorithm and shift. */
+int pimdb_get_algorithm(pimdb_t h, int *algorithm, int *shift);
 
 /* Launch shape override: threads per workgroup (64, 128, 256, 512 or 1024)
  * and particles owned per thread in the recursions (1, 2, 4 or 8; 4 and 8 need

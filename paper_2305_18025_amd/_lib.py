@@ -23,6 +23,10 @@ PIMDB_ERANGE = -6
 PIMDB_FP64 = 0
 PIMDB_MIXED = 1
 PIMDB_FP64_DIRECT = 2
+PIMDB_ALG_FAST = 0
+PIMDB_ALG_ORIGINAL = 1
+PIMDB_SHIFT_MIN = 0
+PIMDB_SHIFT_TWO_TERM = 1
 
 STATUS_NONFINITE_INPUT = 1
 STATUS_NONFINITE_OUTPUT = 2
@@ -54,6 +58,8 @@ SIGNATURES = {
     "pimdb_set_box": (_c_int, [_handle, _c_dbl]),
     "pimdb_set_trap": (_c_int, [_handle, _c_dbl]),
     "pimdb_set_precision": (_c_int, [_handle, _c_int]),
+    "pimdb_set_algorithm": (_c_int, [_handle, _c_int, _c_int]),
+    "pimdb_get_algorithm": (_c_int, [_handle, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]),
     "pimdb_set_tuning": (_c_int, [_handle, _c_int, _c_int]),
     "pimdb_set_timing": (_c_int, [_handle, _c_int]),
     "pimdb_last_timing": (_c_int, [_handle, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),

@@ -34,7 +34,7 @@ class BosonicExchange:
     """
 
     def __init__(self, N, P, beta, m=1.0, omega_p=None, *, device=0, box=0.0, trap=0.0,
-                 precision="fp64", threads=0, per_thread=0, split=-1):
+                 precision="fp64", threads=0, per_thread=0, split=-1, algorithm="fast", shift="min"):
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("BosonicExchange needs a GPU")
@@ -70,6 +70,8 @@ class BosonicExchange:
             check(self.lib.pimdb_set_tuning(h, int(threads), int(per_thread)), h)
         if split != -1:
             check(self.lib.pimdb_set_split(h, int(split)), h)
+        if algorithm != "fast" or shift != "min":
+            self._set_algorithm(algorithm, shift)
         self._bind()
 
     # ------------------------------------------------------------ plumbing
@@ -92,6 +94,29 @@ class BosonicExchange:
         library keeps their tables and this object their workspace."""
         check(self.lib.pimdb_set_tuning(self._h, int(threads), int(per_thread)), self._h)
         self._bind()
+
+    _ALG = {"fast": _lib.PIMDB_ALG_FAST, "original": _lib.PIMDB_ALG_ORIGINAL}
+    _SHIFT = {"min": _lib.PIMDB_SHIFT_MIN, "two_term": _lib.PIMDB_SHIFT_TWO_TERM}
+
+    def _set_algorithm(self, algorithm, shift):
+        if algorithm not in self._ALG or shift not in self._SHIFT:
+            raise ValueError("algorithm must be 'fast' or 'original', shift 'min' or 'two_term'")
+        check(self.lib.pimdb_set_algorithm(self._h, self._ALG[algorithm], self._SHIFT[shift]), self._h)
+
+    def set_algorithm(self, algorithm: str, shift: str = "min"):
+        """'fast' (the quadratic algorithm, default) or 'original' (the cubic
+        comparison path, O(P N^3) time and O(P N^2) workspace); shift 'min' or
+        'two_term' selects the original algorithm's shift of the forward
+        recurrence.  Rebinds the workspace."""
+        self._set_algorithm(algorithm, shift)
+        self._bind()
+
+    @property
+    def algorithm(self):
+        a, s = ctypes.c_int(), ctypes.c_int()
+        check(self.lib.pimdb_get_algorithm(self._h, ctypes.byref(a), ctypes.byref(s)), self._h)
+        inv = {v: k for k, v in self._ALG.items()}, {v: k for k, v in self._SHIFT.items()}
+        return inv[0][a.value], inv[1][s.value]
 
     def set_timing(self, enable: bool = True):
         """Record HIP events around the exchange and finalize launches of

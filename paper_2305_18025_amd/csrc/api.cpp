@@ -61,6 +61,13 @@ struct pimdb_ctx {
     int helpers_total = 0; // helper workgroups of a forces launch
     int cus = 0;           // compute units of the device
     uint64_t wait_ticks = 200000000ull; // split waits give up after 2 s (100 MHz clock)
+    // algorithm: the quadratic one, or the original cubic one (comparison
+    // path) with its shift of the forward recurrence; the original one's
+    // per-system workspace regions (offsets in doubles)
+    int algorithm = PIMDB_ALG_FAST;
+    int shift = PIMDB_SHIFT_MIN;
+    std::vector<int64_t> orig_ws;
+    int64_t orig_doubles = 0;
     // workspace
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -328,6 +335,19 @@ int build_tables(pimdb_t h) {
     h->total_elems = off;
     h->ws_doubles = ws;
     h->st_doubles = st;
+    // the original algorithm's regions (only when it is selected: O(P N^2)
+    // doubles per system); the two layouts share the workspace, which is
+    // sized for the larger
+    h->orig_ws.assign(S, 0);
+    h->orig_doubles = 0;
+    if (h->algorithm == PIMDB_ALG_ORIGINAL) {
+        int64_t o = 0;
+        for (int s = 0; s < S; ++s) {
+            h->orig_ws[s] = o;
+            o += round_up(OrigLayout::total(h->N[s], h->P[s]), 32);
+        }
+        h->orig_doubles = o;
+    }
 
     // schedule: recursion items by decreasing N (forward and backward of a
     // system adjacent), then the spring items.
@@ -390,7 +410,7 @@ int build_tables(pimdb_t h) {
 }
 
 size_t ws_bytes_needed(pimdb_t h) {
-    return (size_t)(WS_HEADER_BYTES + h->ws_doubles * 8);
+    return (size_t)(WS_HEADER_BYTES + std::max(h->ws_doubles, h->orig_doubles) * 8);
 }
 
 int check_ready(pimdb_t h) {
@@ -439,6 +459,48 @@ int run(pimdb_t h, LaunchArgs &a, const Item *items, int n) {
     if (tm && (e = hipEventRecord(h->ev[2], h->stream)) != hipSuccess) return hip_fail(h, e, "event");
     h->ev_recorded = tm;
     return PIMDB_OK;
+}
+
+// The original algorithm, system after system (forces null: energy only).
+int run_original(pimdb_t h, const double *pos, double *forces, double *energy) {
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, PIMDB_EDEVICE, "cannot select device");
+    h->status_ws = h->ws;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(h->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) h->captured = true;
+    const bool tm = h->timing && cs == hipStreamCaptureStatusNone;
+    hipError_t e;
+    if (tm && (e = hipEventRecord(h->ev[0], h->stream)) != hipSuccess) return hip_fail(h, e, "event");
+    for (int s = 0; s < h->S; ++s) {
+        const SysDesc &d = h->desc[s];
+        OrigArgs a{};
+        a.pos = pos + d.off;
+        a.out = forces ? forces + d.off : nullptr;
+        a.energy = energy ? energy + s : nullptr;
+        a.ws = (double *)(h->ws + WS_HEADER_BYTES) + h->orig_ws[s];
+        a.flags = (int32_t *)h->ws;
+        a.N = d.N;
+        a.P = d.P;
+        a.beta = d.beta;
+        a.k = d.k;
+        a.mw2 = d.mw2;
+        a.box = h->box;
+        a.inv_box = h->box > 0 ? 1.0 / h->box : 0.0;
+        a.trapc = d.m * h->trap_w * h->trap_w / (double)d.P;
+        a.two_term = h->shift == PIMDB_SHIFT_TWO_TERM;
+        if ((e = launch_original(a, h->stream)) != hipSuccess) return hip_fail(h, e, "original algorithm launch");
+    }
+    if (tm) {
+        if ((e = hipEventRecord(h->ev[1], h->stream)) != hipSuccess) return hip_fail(h, e, "event");
+        if ((e = hipEventRecord(h->ev[2], h->stream)) != hipSuccess) return hip_fail(h, e, "event");
+    }
+    h->ev_recorded = tm;
+    return PIMDB_OK;
+}
+
+int fast_only(pimdb_t h) {
+    return h->algorithm == PIMDB_ALG_FAST ? PIMDB_OK
+                                          : fail(h, PIMDB_EINVAL, "not available with the original algorithm");
 }
 
 int set_batch_impl(pimdb_t h, int32_t S, const int64_t *N, const int32_t *P, const double *beta,
@@ -548,6 +610,26 @@ int pimdb_set_precision(pimdb_t h, int mode) {
     if (mode != PIMDB_FP64 && mode != PIMDB_MIXED && mode != PIMDB_FP64_DIRECT)
         return fail(h, PIMDB_EINVAL, "unknown precision mode");
     h->precision = mode;
+    return PIMDB_OK;
+}
+
+int pimdb_set_algorithm(pimdb_t h, int algorithm, int shift) {
+    if (!h) return PIMDB_EINVAL;
+    if (algorithm != PIMDB_ALG_FAST && algorithm != PIMDB_ALG_ORIGINAL)
+        return fail(h, PIMDB_EINVAL, "unknown algorithm");
+    if (shift != PIMDB_SHIFT_MIN && shift != PIMDB_SHIFT_TWO_TERM) return fail(h, PIMDB_EINVAL, "unknown shift");
+    if (algorithm == PIMDB_ALG_FAST && shift != PIMDB_SHIFT_MIN)
+        return fail(h, PIMDB_EINVAL, "the quadratic algorithm takes no shift (its sums carry their own exponents)");
+    h->algorithm = algorithm;
+    h->shift = shift;
+    if (h->S > 0) return build_tables(h);
+    return PIMDB_OK;
+}
+
+int pimdb_get_algorithm(pimdb_t h, int *algorithm, int *shift) {
+    if (!h || !algorithm || !shift) return PIMDB_EINVAL;
+    *algorithm = h->algorithm;
+    *shift = h->shift;
     return PIMDB_OK;
 }
 
@@ -667,6 +749,7 @@ int pimdb_exchange_energy(pimdb_t h, const double *pos, double *energy) {
     int rc = check_ready(h);
     if (rc) return rc;
     if (!pos || !energy) return fail(h, PIMDB_EINVAL, "null pointer");
+    if (h->algorithm == PIMDB_ALG_ORIGINAL) return run_original(h, pos, nullptr, energy);
     LaunchArgs a = base_args(h, h->ws);
     a.pos = pos;
     a.energy = energy;
@@ -679,6 +762,7 @@ int pimdb_exchange_forces(pimdb_t h, const double *pos, double *forces, double *
     if (rc) return rc;
     if (!pos || !forces) return fail(h, PIMDB_EINVAL, "null pointer");
     if (pos == forces) return fail(h, PIMDB_EINVAL, "positions and forces alias");
+    if (h->algorithm == PIMDB_ALG_ORIGINAL) return run_original(h, pos, forces, energy);
     LaunchArgs a = base_args(h, h->ws);
     a.pos = pos;
     a.out = forces;
@@ -691,6 +775,7 @@ int pimdb_exchange_forces_batched(pimdb_t h, const double *pos_packed, const int
                                   double *forces_packed, double *energies) {
     int rc = check_ready(h);
     if (rc) return rc;
+    if ((rc = fast_only(h))) return rc;
     if (!pos_packed || !offsets_dev || !forces_packed || !energies) return fail(h, PIMDB_EINVAL, "null pointer");
     if (pos_packed == forces_packed) return fail(h, PIMDB_EINVAL, "positions and forces alias");
     LaunchArgs a = base_args(h, h->ws);
@@ -705,6 +790,7 @@ int pimdb_exchange_forces_batched(pimdb_t h, const double *pos_packed, const int
 int pimdb_exchange_forces_static(pimdb_t h, const double *pos, double *forces, double *energy) {
     if (!h) return PIMDB_EINVAL;
     if (h->S <= 0) return fail(h, PIMDB_ENOSYS, "no system set");
+    if (fast_only(h)) return PIMDB_EINVAL;
     if (!pos || !forces) return fail(h, PIMDB_EINVAL, "null pointer");
     if (pos == forces) return fail(h, PIMDB_EINVAL, "positions and forces alias");
     const size_t need = ws_bytes_needed(h);
@@ -733,6 +819,7 @@ int pimdb_exchange_forces_static(pimdb_t h, const double *pos, double *forces, d
 int pimdb_exchange_energy_save(pimdb_t h, const double *pos, double *energy, void *state) {
     int rc = check_ready(h);
     if (rc) return rc;
+    if ((rc = fast_only(h))) return rc;
     if (!pos || !energy || !state) return fail(h, PIMDB_EINVAL, "null pointer");
     LaunchArgs a = base_args(h, h->ws);
     a.pos = pos;
@@ -746,6 +833,7 @@ int pimdb_exchange_adjoint(pimdb_t h, const double *pos, const void *state, cons
                            double *grad_pos) {
     int rc = check_ready(h);
     if (rc) return rc;
+    if ((rc = fast_only(h))) return rc;
     if (!pos || !state || !grad_energy || !grad_pos) return fail(h, PIMDB_EINVAL, "null pointer");
     if (pos == grad_pos) return fail(h, PIMDB_EINVAL, "positions and gradient alias");
     LaunchArgs a = base_args(h, h->ws);

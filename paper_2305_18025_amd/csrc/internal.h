@@ -147,6 +147,50 @@ struct EChunk {
     int64_t begin, end; // element range in packed arrays
 };
 
+// Workspace of the original (cubic) algorithm for one system of N
+// particles with P beads, offsets in doubles from the system's region; NB =
+// 3 P N right-hand sides (bead derivatives), b = ((l-1) P + j-1) 3 + c:
+//   ein[N]        interior spring sums of each particle (without k)
+//   lnk[N]        link spring of particle l to l+1 (without k; 0 for l = N)
+//   V[N+1]        V^[1,v], v = 0..N
+//   Et[N][N]      [v-1][u-1] = E^[u,v] for u <= v, 0 above
+//   Er[N][N]      [u-1][v-1] = E^[u,v] (the transpose)
+//   W[N][N]       [g][v-1] = weight of cycle [g+1, v] in V^[1,v] (g < v), 0 else
+//   C[N+1][N]     [L][v-1] = sum_{g < L} W[g][v-1]
+//   T[N][3]       last-bead derivative sums at v = l
+//   G[NB/256][N][256]  [b/256][v-1][b%256] = dV^[1,v] / dx_b, stored for v >= l(b)
+//                 (the 256 right-hand sides of a workgroup contiguous per v:
+//                 its history is one contiguous region)
+struct OrigLayout {
+    static __host__ __device__ inline int64_t ein(int64_t N) { return 0; }
+    static __host__ __device__ inline int64_t lnk(int64_t N) { return N; }
+    static __host__ __device__ inline int64_t V(int64_t N) { return 2 * N; }
+    static __host__ __device__ inline int64_t Et(int64_t N) { return 3 * N + 1; }
+    static __host__ __device__ inline int64_t Er(int64_t N) { return Et(N) + N * N; }
+    static __host__ __device__ inline int64_t W(int64_t N) { return Er(N) + N * N; }
+    static __host__ __device__ inline int64_t C(int64_t N) { return W(N) + N * N; }
+    static __host__ __device__ inline int64_t T(int64_t N) { return C(N) + (N + 1) * N; }
+    static __host__ __device__ inline int64_t G(int64_t N) { return (T(N) + 3 * N + 31) / 32 * 32; }
+    static __host__ __device__ inline int64_t G_rhs(int64_t N, int64_t P) { return (3 * P * N + 255) / 256 * 256; }
+    static __host__ __device__ inline int64_t total(int64_t N, int64_t P) { return G(N) + N * G_rhs(N, P); }
+};
+
+// One system's evaluation by the original algorithm.
+struct OrigArgs {
+    const double *pos;  // the system's (P,3,N) positions
+    double *out;        // its forces (null: energy only)
+    double *energy;     // its energy (may be null)
+    double *ws;         // its OrigLayout region
+    int32_t *flags;     // status word
+    int32_t N, P;
+    double beta, k, mw2;
+    double box, inv_box;
+    double trapc;       // trap force coefficient m w^2 / P (0 = none)
+    int32_t two_term;   // 1: the two-candidate shift of the forward recurrence
+    int32_t pad;
+};
+hipError_t launch_original(const OrigArgs &a, hipStream_t st);
+
 hipError_t launch_md_update(const SysDesc *sys, const EChunk *chunks, int nchunks, double *pos,
                             double *vel, const double *forces, double dt, int drift, hipStream_t st);
 hipError_t launch_debug_prefix(const LaunchArgs &a, int s, int threads, hipStream_t st);
