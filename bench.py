@@ -204,6 +204,44 @@ def extra_workloads(steps):
     return out
 
 
+def fast_vs_original(sizes=(32, 64, 128, 256, 512, 1024), P=32, beta=1.0, trap=1.0):
+    """Time per evaluation (energy and forces of one system, HIP events over
+    the calls) of the quadratic algorithm and of the original cubic one on
+    the same GPU, for cold trapped systems of N particles with P = 32 beads
+    (the scaling benchmark's setting), and the log-log slopes."""
+    import numpy as np
+    import torch
+    from paper_2305_18025_amd import BosonicExchange, inputs
+    rows = []
+    for n in sizes:
+        x = inputs.System(inputs.gaussian_system(n, P, seed=n), beta=beta)
+        t = {}
+        for alg in ("fast", "original"):
+            eng = BosonicExchange(n, P, beta, trap=trap, algorithm=alg)
+            pos = eng.pack(x.R)
+            F = eng.empty()
+            E = torch.empty(1, dtype=torch.float64, device=eng.device)
+            eng.forces(pos, out=F, energy=E)
+            torch.cuda.synchronize()
+            reps = 50 if alg == "fast" else max(3, min(50, int(200 * (64.0 / n) ** 2)))
+            t[alg] = time_calls(lambda: eng.forces(pos, out=F, energy=E), reps)
+            if eng.status() != 0:
+                raise RuntimeError("device status set in the %s algorithm at N=%d" % (alg, n))
+            del eng, pos, F, E
+            torch.cuda.empty_cache()
+        rows.append({"N": n, "fast_ms": t["fast"], "original_ms": t["original"],
+                     "speedup": t["original"] / t["fast"]})
+    lg = lambda key: np.polyfit(np.log([r["N"] for r in rows]), np.log([r[key] for r in rows]), 1)[0]
+    tail = rows[-3:]
+    lgt = lambda key: np.polyfit(np.log([r["N"] for r in tail]), np.log([r[key] for r in tail]), 1)[0]
+    return {"P": P, "beta": beta, "trap": trap, "rows": rows,
+            "loglog_slope_all": {"fast": lg("fast_ms"), "original": lg("original_ms"), "speedup": lg("speedup")},
+            "loglog_slope_last3": {"fast": lgt("fast_ms"), "original": lgt("original_ms"),
+                                   "speedup": lgt("speedup")},
+            "description": "one system per call, no graph; the original algorithm's cycle energies by "
+                           "their defining sum, its forces by the per-bead derivative recurrence"}
+
+
 def host_info():
     model = ""
     try:
@@ -431,6 +469,7 @@ def main():
                                   "springs_TB_per_s": spring_bytes / sec_d / 1e12,
                                   "springs_frac_of_8TBs": spring_bytes / sec_d / 8e12}
         out.update(extra_workloads(args.steps))
+        out["fast_vs_original"] = fast_vs_original()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out))
