@@ -242,6 +242,44 @@ def fast_vs_original(sizes=(32, 64, 128, 256, 512, 1024), P=32, beta=1.0, trap=1
                            "their defining sum, its forces by the per-bead derivative recurrence"}
 
 
+# Algorithmic work of the scaled pair interaction per unordered pair: the
+# displacement and its square (3 + 5 flops), the exponent (1), the
+# exponential (EXP_FLOPS), the energy (1) and the two beads' forces (2 x 3
+# fused multiply-adds).
+PAIR_FLOPS = 3 + 5 + 1 + EXP_FLOPS + 1 + 12
+
+
+def pair_interaction(steps=10, g=3.0, sigma=0.5):
+    """The scaled Gaussian pair interaction alone (pimdb_pair_forces) on the
+    periodic N=4096, P=64 system and on the headline batch, HIP events over
+    the calls; its ALU roofline by the unordered-pair count."""
+    import torch
+    from paper_2305_18025_amd import BosonicExchange, inputs
+    out = {}
+    x = inputs.config_large()
+    head = [inputs.System(R, beta=BETA) for R in systems(256)]
+    cases = [("large_periodic", [x], x.box), ("headline_batch_256", head, 0.0)]
+    for name, sys_, box in cases:
+        eng = BosonicExchange([q.N for q in sys_], [q.P for q in sys_], [q.beta for q in sys_],
+                              [q.m for q in sys_], [q.omegaP for q in sys_], box=box, pair=(g, sigma))
+        pos = eng.pack([q.R for q in sys_])
+        F = eng.empty()
+        E = torch.empty(eng.S, dtype=torch.float64, device=eng.device)
+        ms = time_calls(lambda: eng.pair_forces(pos, out=F, energy=E), steps)
+        if eng.status() != 0:
+            raise RuntimeError("device status set in the pair interaction")
+        pairs = sum(q.P * q.N * (q.N - 1) / 2 for q in sys_)
+        fl = pairs * PAIR_FLOPS
+        out[name] = {"systems": len(sys_), "N": sys_[0].N, "P": sys_[0].P, "box": box, "ms_per_call": ms,
+                     "unordered_pairs": pairs, "pairs_per_s": pairs / (ms * 1e-3),
+                     "tflops": fl / (ms * 1e-3) / 1e12, "frac_of_fp64_peak": fl / (ms * 1e-3) / PEAK_FP64}
+        del eng, pos, F, E
+        torch.cuda.empty_cache()
+    out["flops_per_pair"] = PAIR_FLOPS
+    out["U"] = {"g": g, "sigma": sigma, "form": "g exp(-r^2 / (2 sigma^2)), caller-parameterised"}
+    return out
+
+
 def host_info():
     model = ""
     try:
@@ -470,6 +508,7 @@ def main():
                                   "springs_frac_of_8TBs": spring_bytes / sec_d / 8e12}
         out.update(extra_workloads(args.steps))
         out["fast_vs_original"] = fast_vs_original()
+        out["pair_interaction"] = pair_interaction()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out))

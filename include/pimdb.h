@@ -181,6 +181,29 @@ int pimdb_set_trap(pimdb_t h, double w);
  * otherwise.  Takes effect at the next evaluation call. */
 int pimdb_set_precision(pimdb_t h, int mode);
 
+/* Scaled pair interaction (Theory, the bosonic partition function, where
+ * each imaginary-time slice's interaction enters scaled by 1/P):
+ *   U-bar = (1/P) sum_{j=1}^{P} sum_{a<b} U(|r_a^j - r_b^j|),
+ * with the caller's Gaussian U(r) = g exp(-r^2 / (2 sigma^2)) (the form of
+ * a Gaussian repulsion; g and sigma are the caller's, no parameter of the
+ * paper's systems is assumed), minimum image in a periodic box.  Once set
+ * (g != 0), every evaluation that writes forces or energies adds
+ * -grad U-bar and U-bar to them: pimdb_exchange_forces, _energy, _batched,
+ * _static, _energy_save, _adjoint (its gradient), pimdb_md_step and
+ * pimdb_distinguishable_forces, under either algorithm.  O(P N^2) pair
+ * terms per system, in FP64 whatever the precision mode.  g = 0 (default)
+ * removes it.  With a system set this rebuilds the tables and unbinds the
+ * workspace like pimdb_set_batch (the workspace grows by one double per
+ * pair workgroup).  PIMDB_EINVAL for non-finite g, or sigma <= 0 or
+ * non-finite with g != 0. */
+int pimdb_set_pair_gaussian(pimdb_t h, double g, double sigma);
+
+/* The pair interaction alone: forces = -grad U-bar (P,3,N layout, may be
+ * NULL) and energies = U-bar (may be NULL), overwritten.  Asynchronous like
+ * the evaluations.  PIMDB_EINVAL when no pair interaction is set or both
+ * outputs are NULL. */
+int pimdb_pair_forces(pimdb_t h, const double *pos, double *forces, double *energy);
+
 /* Select the algorithm of pimdb_exchange_forces, pimdb_exchange_energy and
  * pimdb_md_step.  PIMDB_ALG_ORIGINAL evaluates the original method of the
  * appendix "Algorithm Pseudocode" (Background, "cubic scaling bosonic

@@ -59,6 +59,8 @@ SIGNATURES = {
     "pimdb_set_trap": (_c_int, [_handle, _c_dbl]),
     "pimdb_set_precision": (_c_int, [_handle, _c_int]),
     "pimdb_set_algorithm": (_c_int, [_handle, _c_int, _c_int]),
+    "pimdb_set_pair_gaussian": (_c_int, [_handle, ctypes.c_double, ctypes.c_double]),
+    "pimdb_pair_forces": (_c_int, [_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pimdb_get_algorithm": (_c_int, [_handle, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]),
     "pimdb_set_tuning": (_c_int, [_handle, _c_int, _c_int]),
     "pimdb_set_timing": (_c_int, [_handle, _c_int]),

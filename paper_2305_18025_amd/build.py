@@ -55,6 +55,7 @@ def jobs():
                     ["-DPIMDB_J=%d" % j, "-DPIMDB_BOX=%d" % box, "-DPIMDB_MIXED=%d" % mixed], obj))
     out.append((os.path.join(CSRC, "kernels.hip"), [], os.path.join(CSRC, "kernels.o")))
     out.append((os.path.join(CSRC, "original.hip"), [], os.path.join(CSRC, "original.o")))
+    out.append((os.path.join(CSRC, "pair.hip"), [], os.path.join(CSRC, "pair.o")))
     out.append((os.path.join(CSRC, "api.cpp"), [], os.path.join(CSRC, "api.o")))
     return out
 

@@ -34,7 +34,8 @@ class BosonicExchange:
     """
 
     def __init__(self, N, P, beta, m=1.0, omega_p=None, *, device=0, box=0.0, trap=0.0,
-                 precision="fp64", threads=0, per_thread=0, split=-1, algorithm="fast", shift="min"):
+                 precision="fp64", threads=0, per_thread=0, split=-1, algorithm="fast", shift="min",
+                 pair=None):
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("BosonicExchange needs a GPU")
@@ -72,6 +73,10 @@ class BosonicExchange:
             check(self.lib.pimdb_set_split(h, int(split)), h)
         if algorithm != "fast" or shift != "min":
             self._set_algorithm(algorithm, shift)
+        self.pair = None
+        if pair is not None:
+            self.pair = (float(pair[0]), float(pair[1]))
+            check(self.lib.pimdb_set_pair_gaussian(h, self.pair[0], self.pair[1]), h)
         self._bind()
 
     # ------------------------------------------------------------ plumbing
@@ -110,6 +115,23 @@ class BosonicExchange:
         recurrence.  Rebinds the workspace."""
         self._set_algorithm(algorithm, shift)
         self._bind()
+
+    def set_pair_gaussian(self, g: float, sigma: float = 1.0):
+        """Add the scaled pair interaction (1/P) sum_j sum_{a<b} g exp(-r^2 /
+        (2 sigma^2)) to every later evaluation (g = 0 removes it).  Rebinds
+        the workspace."""
+        check(self.lib.pimdb_set_pair_gaussian(self._h, float(g), float(sigma)), self._h)
+        self.pair = (float(g), float(sigma)) if g != 0 else None
+        self._bind()
+
+    def pair_forces(self, pos, out=None, energy=None):
+        """The pair interaction alone: (forces, energies)."""
+        out = self.empty() if out is None else out
+        energy = torch.empty(self.S, dtype=torch.float64, device=self.device) if energy is None else energy
+        self._stream()
+        check(self.lib.pimdb_pair_forces(self._h, self._ptr(pos, self.total, "pos"), self._ptr(out, self.total, "forces"),
+                                         self._ptr(energy, self.S, "energy")), self._h)
+        return out, energy
 
     @property
     def algorithm(self):

@@ -68,6 +68,13 @@ struct pimdb_ctx {
     int shift = PIMDB_SHIFT_MIN;
     std::vector<int64_t> orig_ws;
     int64_t orig_doubles = 0;
+    // scaled pair interaction (g = 0: none): its work items, the first item
+    // of each system, and the energy partials' offset in the workspace
+    double pair_g = 0.0, pair_sigma = 1.0;
+    PairItem *d_pitems = nullptr;
+    int32_t *d_pbeg = nullptr;
+    int n_pitems = 0, pair_iblock = 256;
+    int64_t pair_off = 0;
     // workspace
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -249,7 +256,8 @@ int auto_split(pimdb_t h, SplitPlan &p) {
 // Release the current tables: freed at once, or kept until pimdb_destroy
 // if a graph may hold them.
 void free_tables(pimdb_t h, bool all = false) {
-    for (void *p : {(void *)h->d_desc, (void *)h->d_items, (void *)h->d_echunks}) {
+    for (void *p : {(void *)h->d_desc, (void *)h->d_items, (void *)h->d_echunks, (void *)h->d_pitems,
+                    (void *)h->d_pbeg}) {
         if (!p) continue;
         if (h->captured && !all)
             h->retired.push_back(p);
@@ -263,7 +271,9 @@ void free_tables(pimdb_t h, bool all = false) {
     h->d_desc = nullptr;
     h->d_items = nullptr;
     h->d_echunks = nullptr;
-    h->n_fb = h->n_f = h->n_b = h->n_s = h->n_echunks = 0;
+    h->d_pitems = nullptr;
+    h->d_pbeg = nullptr;
+    h->n_fb = h->n_f = h->n_b = h->n_s = h->n_echunks = h->n_pitems = 0;
 }
 
 // Build descriptors, the launch schedule (largest systems first) and the MD
@@ -348,6 +358,25 @@ int build_tables(pimdb_t h) {
         }
         h->orig_doubles = o;
     }
+    // pair interaction items: every slice of every system in particle blocks
+    // of the widest size that still gives 2048 workgroups (or 64)
+    std::vector<PairItem> pit;
+    std::vector<int32_t> pbeg;
+    if (h->pair_g != 0.0) {
+        int ib = 256;
+        for (; ib > 64; ib /= 2) {
+            int64_t n = 0;
+            for (int s = 0; s < S; ++s) n += (int64_t)h->P[s] * ((h->N[s] + ib - 1) / ib);
+            if (n >= 2048) break;
+        }
+        h->pair_iblock = ib;
+        for (int s = 0; s < S; ++s) {
+            pbeg.push_back((int32_t)pit.size());
+            for (int j = 0; j < h->P[s]; ++j)
+                for (int64_t i0 = 0; i0 < h->N[s]; i0 += ib) pit.push_back(PairItem{s, j, (int32_t)i0, 0});
+        }
+        pbeg.push_back((int32_t)pit.size());
+    }
 
     // schedule: recursion items by decreasing N (forward and backward of a
     // system adjacent), then the spring items.
@@ -396,6 +425,8 @@ int build_tables(pimdb_t h) {
     h->n_b = (int)(b.size() + sp.size());
     h->n_s = (int)sp.size();
     h->n_echunks = (int)ec.size();
+    h->n_pitems = (int)pit.size();
+    h->pair_off = std::max(h->ws_doubles, h->orig_doubles);
     hipError_t e;
     if ((e = hipMalloc(&h->d_desc, sizeof(SysDesc) * S)) != hipSuccess) return hip_fail(h, e, "hipMalloc");
     if ((e = hipMalloc(&h->d_items, sizeof(Item) * all.size())) != hipSuccess) return hip_fail(h, e, "hipMalloc");
@@ -406,11 +437,19 @@ int build_tables(pimdb_t h) {
         return hip_fail(h, e, "hipMemcpy");
     if ((e = hipMemcpy(h->d_echunks, ec.data(), sizeof(EChunk) * ec.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(h, e, "hipMemcpy");
+    if (!pit.empty()) {
+        if ((e = hipMalloc(&h->d_pitems, sizeof(PairItem) * pit.size())) != hipSuccess) return hip_fail(h, e, "hipMalloc");
+        if ((e = hipMalloc(&h->d_pbeg, sizeof(int32_t) * pbeg.size())) != hipSuccess) return hip_fail(h, e, "hipMalloc");
+        if ((e = hipMemcpy(h->d_pitems, pit.data(), sizeof(PairItem) * pit.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(h, e, "hipMemcpy");
+        if ((e = hipMemcpy(h->d_pbeg, pbeg.data(), sizeof(int32_t) * pbeg.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(h, e, "hipMemcpy");
+    }
     return PIMDB_OK;
 }
 
 size_t ws_bytes_needed(pimdb_t h) {
-    return (size_t)(WS_HEADER_BYTES + std::max(h->ws_doubles, h->orig_doubles) * 8);
+    return (size_t)(WS_HEADER_BYTES + (std::max(h->ws_doubles, h->orig_doubles) + h->n_pitems) * 8);
 }
 
 int check_ready(pimdb_t h) {
@@ -441,6 +480,33 @@ const Item *items_f(pimdb_t h) { return h->d_items + h->n_fb; }
 const Item *items_b(pimdb_t h) { return h->d_items + h->n_fb + h->n_f; }
 const Item *items_s(pimdb_t h) { return h->d_items + h->n_fb + h->n_f + h->n_b; }
 
+// The pair interaction on top of what an evaluation wrote (accumulate = 1),
+// or alone; sign -1 with gscale: the adjoint's gradient.
+hipError_t run_pair(pimdb_t h, char *ws, const double *pos, double *out, double *energy, const int64_t *offs,
+                    const double *gscale, int sign, int accumulate) {
+    if (h->pair_g == 0.0 || h->n_pitems == 0 || (!out && !energy)) return hipSuccess;
+    PairArgs p{};
+    p.sys = h->d_desc;
+    p.items = h->d_pitems;
+    p.beg = h->d_pbeg;
+    p.offs = offs;
+    p.pos = pos;
+    p.out = out;
+    p.energy = energy;
+    p.epart = (double *)(ws + WS_HEADER_BYTES) + h->pair_off;
+    p.gscale = gscale;
+    p.flags = (int32_t *)ws;
+    p.box = h->box;
+    p.inv_box = h->box > 0 ? 1.0 / h->box : 0.0;
+    p.c2 = -1.4426950408889634 / (2.0 * h->pair_sigma * h->pair_sigma);
+    p.g = h->pair_g;
+    p.inv_s2 = 1.0 / (h->pair_sigma * h->pair_sigma);
+    p.sign = sign;
+    p.accumulate = accumulate;
+    p.iblock = h->pair_iblock;
+    return launch_pair(p, h->n_pitems, h->S, h->stream);
+}
+
 int run(pimdb_t h, LaunchArgs &a, const Item *items, int n) {
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, PIMDB_EDEVICE, "cannot select device");
@@ -456,6 +522,13 @@ int run(pimdb_t h, LaunchArgs &a, const Item *items, int n) {
     if (tm && (e = hipEventRecord(h->ev[1], h->stream)) != hipSuccess) return hip_fail(h, e, "event");
     e = launch_finalize(a, h->S, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "finalize launch");
+    {
+        const bool adj = (a.mode & M_ADJOINT) != 0;
+        double *po = (a.mode & M_FORCES) ? a.out : nullptr;
+        double *pe = (a.mode & M_ENERGY) ? a.energy : nullptr;
+        e = run_pair(h, (char *)a.flags, a.pos, po, pe, a.offs, adj ? a.gscale : nullptr, adj ? -1 : 1, 1);
+        if (e != hipSuccess) return hip_fail(h, e, "pair launch");
+    }
     if (tm && (e = hipEventRecord(h->ev[2], h->stream)) != hipSuccess) return hip_fail(h, e, "event");
     h->ev_recorded = tm;
     return PIMDB_OK;
@@ -490,6 +563,8 @@ int run_original(pimdb_t h, const double *pos, double *forces, double *energy) {
         a.two_term = h->shift == PIMDB_SHIFT_TWO_TERM;
         if ((e = launch_original(a, h->stream)) != hipSuccess) return hip_fail(h, e, "original algorithm launch");
     }
+    if ((e = run_pair(h, h->ws, pos, forces, energy, nullptr, nullptr, 1, 1)) != hipSuccess)
+        return hip_fail(h, e, "pair launch");
     if (tm) {
         if ((e = hipEventRecord(h->ev[1], h->stream)) != hipSuccess) return hip_fail(h, e, "event");
         if ((e = hipEventRecord(h->ev[2], h->stream)) != hipSuccess) return hip_fail(h, e, "event");
@@ -623,6 +698,30 @@ int pimdb_set_algorithm(pimdb_t h, int algorithm, int shift) {
     h->algorithm = algorithm;
     h->shift = shift;
     if (h->S > 0) return build_tables(h);
+    return PIMDB_OK;
+}
+
+int pimdb_set_pair_gaussian(pimdb_t h, double g, double sigma) {
+    if (!h) return PIMDB_EINVAL;
+    if (!std::isfinite(g)) return fail(h, PIMDB_EINVAL, "pair strength must be finite");
+    if (g != 0.0 && !finite_pos(sigma)) return fail(h, PIMDB_EINVAL, "pair width must be finite and positive");
+    h->pair_g = g;
+    h->pair_sigma = g != 0.0 ? sigma : 1.0;
+    if (h->S > 0) return build_tables(h);
+    return PIMDB_OK;
+}
+
+int pimdb_pair_forces(pimdb_t h, const double *pos, double *forces, double *energy) {
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (!pos || (!forces && !energy)) return fail(h, PIMDB_EINVAL, "null pointer");
+    if (pos == forces) return fail(h, PIMDB_EINVAL, "positions and forces alias");
+    if (h->pair_g == 0.0) return fail(h, PIMDB_EINVAL, "no pair interaction set");
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, PIMDB_EDEVICE, "cannot select device");
+    h->status_ws = h->ws;
+    const hipError_t e = run_pair(h, h->ws, pos, forces, energy, nullptr, nullptr, 1, 0);
+    if (e != hipSuccess) return hip_fail(h, e, "pair launch");
     return PIMDB_OK;
 }
 

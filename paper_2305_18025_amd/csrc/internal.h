@@ -191,6 +191,32 @@ struct OrigArgs {
 };
 hipError_t launch_original(const OrigArgs &a, hipStream_t st);
 
+// Scaled pair interaction: one workgroup per item, bead slice j of system
+// sys, particles i0 .. i0 + iblock - 1 against every particle of the slice.
+struct PairItem {
+    int32_t sys, j, i0, pad;
+};
+struct PairArgs {
+    const SysDesc *sys;
+    const PairItem *items;
+    const int32_t *beg;    // first item of each system (S + 1 entries)
+    const int64_t *offs;   // caller's element offset per system, or null: SysDesc::off
+    const double *pos;
+    double *out;           // forces (or the gradient), may be null
+    double *energy;        // per-system energies, may be null
+    double *epart;         // one energy partial per item (workspace)
+    const double *gscale;  // gradient mode: per-system factor (null: 1)
+    int32_t *flags;        // status word
+    double box, inv_box;
+    double c2;             // -log2(e) / (2 sigma^2): exponent of U in log2 units per r^2
+    double g, inv_s2;      // U(0) and 1 / sigma^2
+    int32_t sign;          // +1: forces -dU/dr; -1: the gradient (adjoint)
+    int32_t accumulate;    // 1: add to out and energy; 0: overwrite them
+    int32_t iblock;        // particles per item (the workgroup size)
+    int32_t pad;
+};
+hipError_t launch_pair(const PairArgs &a, int nitems, int S, hipStream_t st);
+
 hipError_t launch_md_update(const SysDesc *sys, const EChunk *chunks, int nchunks, double *pos,
                             double *vel, const double *forces, double dt, int drift, hipStream_t st);
 hipError_t launch_debug_prefix(const LaunchArgs &a, int s, int threads, hipStream_t st);
