@@ -342,11 +342,8 @@ def cpu_baseline(seconds, max_threads=16):
 
 
 def device_sources_sha1():
-    """SHA-1 over the device sources (the exchange kernels and the others)."""
-    h = hashlib.sha1()
-    for f in ("common.h", "exchange.h", "exchange_inst.hip", "kernels.hip", "internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_2305_18025_amd", "csrc", f), "rb").read())
-    return h.hexdigest()
+    from paper_2305_18025_amd.profiling import device_sources_sha1 as f
+    return f()
 
 
 def traffic_record(batch):
@@ -375,9 +372,12 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's built-in launch shape instead of timing the candidates")
     ap.add_argument("--plain-calls", type=int, default=1000)
-    ap.add_argument("--profile-run", action="store_true",
-                    help="only replay the headline launch (for rocprofv3 counter runs), then copy a "
-                         "256 MiB buffer once as the traffic calibration kernel")
+    ap.add_argument("--profile-run", nargs="?", const="headline", default=None,
+                    choices=("headline", "original", "pair"),
+                    help="only run one workload for rocprofv3: the headline launch (graph replays, then "
+                         "a 256 MiB copy as the traffic calibration kernel), the original algorithm at "
+                         "N=1024, P=32 (steps calls), or the pair interaction of the periodic N=4096, "
+                         "P=64 system (steps calls)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -387,6 +387,26 @@ def main():
 
     import torch
     from paper_2305_18025_amd.tune import autotune
+
+    if args.profile_run in ("original", "pair"):
+        from paper_2305_18025_amd import BosonicExchange, inputs
+        if args.profile_run == "original":
+            x = inputs.System(inputs.gaussian_system(N_HEAD, P_HEAD, seed=3), beta=BETA)
+            eng = BosonicExchange(x.N, x.P, x.beta, trap=1.0, algorithm="original")
+        else:
+            x = inputs.config_large()
+            eng = BosonicExchange(x.N, x.P, x.beta, x.m, x.omegaP, box=x.box, pair=(3.0, 0.5))
+        pos = eng.pack(x.R)
+        F = eng.empty()
+        E = torch.empty(1, dtype=torch.float64, device=eng.device)
+        run = (lambda: eng.forces(pos, out=F, energy=E)) if args.profile_run == "original" else \
+            (lambda: eng.pair_forces(pos, out=F, energy=E))
+        for _ in range(args.warmup + args.steps):
+            run()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": args.profile_run, "calls": args.warmup + args.steps,
+                          "status": eng.status()}))
+        return
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     B = args.batch
