@@ -1,6 +1,6 @@
-"""Scaled pair interaction U-bar -- CPU oracle (test infrastructure only:
-tests, the smoke check and the bench's CPU baseline use it; the library
-never does).
+"""Scaled pair interaction U-bar and the closing-spring table -- CPU oracle
+(test infrastructure only: tests, the smoke check and the bench's CPU
+baseline use it; the library never does).
 
 The paper's partition function weights every imaginary-time slice with the
 interaction scaled by 1/P (Theory, the bosonic partition function):
@@ -61,6 +61,20 @@ def pair_gaussian_at(R, g, sigma, L, a, j):
     U = g * np.exp(-(D * D).sum(axis=1) / (2.0 * sigma * sigma))
     U[a] = 0.0
     return (U[:, None] * D).sum(axis=0) / (sigma * sigma) / P
+
+
+def endpoint_springs(R, k, L=0.0):
+    """The closing-spring table s(v, u) = k |r_v^P - r_u^1|^2 for u <= v
+    (Background: the spring that closes the ring of particles u..v runs from
+    bead P of v to bead 1 of u), rows v = 1..N concatenated, each holding
+    u = 1..v; minimum image when L > 0."""
+    R = np.asarray(R, dtype=np.float64)
+    N = R.shape[0]
+    rows = []
+    for v in range(N):
+        d = _image(R[v, -1, None, :] - R[:v + 1, 0, :], L)
+        rows.append(k * (d * d).sum(axis=1))
+    return np.concatenate(rows)
 
 
 def pair_brute(R, g, sigma, L=0.0):

@@ -12,6 +12,7 @@ import pytest
 import torch
 
 import oracle
+from oracle.pair import endpoint_springs
 from paper_2305_18025_amd import BosonicExchange, inputs
 from paper_2305_18025_amd.inputs import System, cube_system, gaussian_system, omega_p
 
@@ -205,10 +206,7 @@ def test_endpoint_spring_table(as_float):
     s = System(R, beta=1.0)
     eng, pos = _engine([s])
     out = eng.endpoint_springs(pos, 0, as_float=as_float).double().cpu().numpy()
-    k = 0.5 * s.m * s.omegaP ** 2
-    d = R[:, -1, None, :] - R[None, :, 0, :]   # [v, u]
-    full = k * (d * d).sum(axis=2)
-    want = np.concatenate([full[v, :v + 1] for v in range(s.N)])
+    want = endpoint_springs(R, 0.5 * s.m * s.omegaP ** 2)
     tol = 1e-7 if as_float else 1e-14
     assert np.abs(out - want).max() <= tol * np.abs(want).max()
 

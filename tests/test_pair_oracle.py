@@ -6,7 +6,8 @@ import math
 import numpy as np
 import pytest
 
-from oracle.pair import pair_brute, pair_gaussian, pair_gaussian_at
+import oracle
+from oracle.pair import endpoint_springs, pair_brute, pair_gaussian, pair_gaussian_at
 from paper_2305_18025_amd.inputs import cube_system, gaussian_system
 
 
@@ -84,3 +85,32 @@ def test_sampled_equals_full():
     _, F = pair_gaussian(R, 2.0, 0.6, L=3.0)
     for a, j in [(0, 0), (17, 3), (49, 1)]:
         assert np.abs(pair_gaussian_at(R, 2.0, 0.6, 3.0, a, j) - F[a, j]).max() <= 1e-14 * np.abs(F).max()
+
+
+@pytest.mark.parametrize("L", [0.0, 3.0])
+def test_endpoint_springs_against_cycle_energies(L):
+    """The closing-spring table against the C oracle's cycle energies E^[u,v]
+    and interior energies: a one-particle ring is its interior springs plus
+    its own closing spring, s(v,v) = E^[v,v] - E_int(v); and for u < v - 1
+    the links cancel in E^[u,v] - E^[u,v-1] - E^[v-1,v] + E_int(v-1)
+    = s(v,u) - s(v-1,u) - s(v,v-1)."""
+    R = cube_system(9, 4, seed=6, side=L if L else None)
+    beta = 1.0
+    w = 2.0
+    o = oracle.alg1(R, beta, 1.0, w, L=L, extras=True)
+    k = 0.5 * w * w
+    flat = endpoint_springs(R, k, L)
+    N = R.shape[0]
+    S = np.zeros((N, N))
+    pos = 0
+    for v in range(N):
+        S[v, :v + 1] = flat[pos:pos + v + 1]
+        pos += v + 1
+    E, Ei = o["E"], o["Eint"]  # E[u-1, v-1] = E^[u,v]
+    scale = np.abs(E).max()
+    for v in range(N):
+        assert abs(S[v, v] - (E[v, v] - Ei[v])) <= 1e-13 * scale
+    for v in range(2, N):
+        for u in range(v - 1):
+            lhs = E[u, v] - E[u, v - 1] - E[v - 1, v] + Ei[v - 1]
+            assert abs(lhs - (S[v, u] - S[v - 1, u] - S[v, v - 1])) <= 1e-12 * scale, (u, v)
