@@ -58,6 +58,7 @@ struct pimdb_ctx {
     int user_split = -1;
     int split_g = 0;       // 0: no system split
     int split_mode = 0;    // launch variant: 0 whole, 1 split, 2 split with a CU per workgroup
+    int split_rows = 0;    // row waves per helper workgroup
     int helpers_total = 0; // helper workgroups of a forces launch
     int cus = 0;           // compute units of the device
     uint64_t wait_ticks = 200000000ull; // split waits give up after 2 s (100 MHz clock)
@@ -189,65 +190,67 @@ void auto_tuning(int64_t Nmax, int S, int &threads, int &per) {
 // 512-thread split kernel and must fit the workgroups the device holds at
 // once, since the chain and helpers of a system wait on each other.
 constexpr int SPLIT_T = 512;
-constexpr int SPLIT_ROWS = SPLIT_T / 64 - 1;
+// A helper's row waves: one per SIMD when every workgroup has a CU of its
+// own (launch mode 2), all but the fetch wave when two share a CU (mode 1).
+int split_rows(int mode) { return mode == 2 ? 4 : SPLIT_T / 64 - 1; }
 
 struct SplitPlan {
     int per = 1;
     int helpers = 0; // per forces launch (both directions)
     int recursion_wgs = 0;
     int mode = 1;    // 2: one workgroup per CU (the plan fits), 1: two per CU
+    int rows = 7;    // a helper's row waves
     std::vector<int> nhelp;
 };
 
-int helpers_for(int64_t N, int g) {
+int helpers_for(int64_t N, int g, int rows) {
     const int nblk = (int)((N + 63) / 64);
     if (nblk < 3 || g < 1) return 0;
     int nh = (nblk - 2 + g - 1) / g;
-    const int most = 2 * SPLIT_ROWS; // blocks a helper can hold with two rows per thread
+    const int most = 2 * rows; // blocks a helper can hold with two rows per thread
     nh = std::max(nh, (nblk - 2 + most - 1) / most);
     return std::min(nh, nblk - 2);
 }
 
-// Plan for blocks-per-helper g; false if it does not fit the device.
+// The plan for g blocks per helper: a CU of its own for every chain and
+// helper when they all fit so (no SIMD shared with another workgroup, four
+// row waves per helper), else two per CU (seven row waves).
 bool plan_split(pimdb_t h, int g, SplitPlan &p) {
     const int S = h->S;
-    p.nhelp.assign(S, 0);
-    p.per = 1;
-    p.helpers = 0;
-    p.recursion_wgs = 0;
-    for (int s = 0; s < S; ++s) {
-        const int nblk = (int)((h->N[s] + 63) / 64);
-        const int nh = helpers_for(h->N[s], g);
-        p.nhelp[s] = nh;
-        if (nh > 0) {
-            const int own = (nblk - 2 + nh - 1) / nh;
-            p.per = std::max(p.per, (own + SPLIT_ROWS - 1) / SPLIT_ROWS);
-        } else {
-            p.per = std::max(p.per, (int)((h->N[s] + SPLIT_T - 1) / SPLIT_T));
-        }
-        p.helpers += 2 * nh;
-        p.recursion_wgs += 2 + 2 * nh;
-    }
-    if (p.per > 2 || p.helpers == 0) return false;
-    // a CU of its own for every chain and helper when they all fit so (no
-    // SIMD shared with another workgroup), else two per CU
     const bool box = h->box > 0 || h->precision == PIMDB_FP64_DIRECT, mixed = h->precision == PIMDB_MIXED;
     for (int mode : {2, 1}) {
+        const int rows = split_rows(mode);
+        p.nhelp.assign(S, 0);
+        p.per = 1;
+        p.helpers = 0;
+        p.recursion_wgs = 0;
+        for (int s = 0; s < S; ++s) {
+            const int nblk = (int)((h->N[s] + 63) / 64);
+            const int nh = helpers_for(h->N[s], g, rows);
+            p.nhelp[s] = nh;
+            if (nh > 0) {
+                const int own = (nblk - 2 + nh - 1) / nh;
+                p.per = std::max(p.per, (own + rows - 1) / rows);
+            } else {
+                p.per = std::max(p.per, (int)((h->N[s] + SPLIT_T - 1) / SPLIT_T));
+            }
+            p.helpers += 2 * nh;
+            p.recursion_wgs += 2 + 2 * nh;
+        }
+        if (p.per > 2 || p.helpers == 0) continue;
         const int occ = exchange_occupancy(box, mixed, SPLIT_T, p.per, mode);
         if (occ > 0 && (int64_t)p.recursion_wgs <= (int64_t)occ * h->cus) {
             p.mode = mode;
+            p.rows = rows;
             return true;
         }
     }
     return false;
 }
 
-// The automatic choice: split only when the whole recursions would leave
-// most CUs idle (fewer than one recursion workgroup per two CUs), with the
-// most helpers (smallest g, from 7 blocks each: one per row wave) that fit.
 int auto_split(pimdb_t h, SplitPlan &p) {
     if (2 * (int64_t)h->S * 2 > h->cus) return 0;
-    for (int g : {7, 14, 28, 56}) {
+    for (int g : {4, 7, 14, 28, 56}) {
         if (plan_split(h, g, p)) return g;
     }
     return 0;
@@ -304,6 +307,7 @@ int build_tables(pimdb_t h) {
         h->split_g = auto_split(h, plan);
     }
     h->split_mode = h->split_g > 0 ? plan.mode : 0;
+    h->split_rows = h->split_g > 0 ? plan.rows : 0;
     if (h->split_g > 0) {
         h->threads = SPLIT_T;
         h->per_thread = plan.per;
@@ -471,6 +475,7 @@ LaunchArgs base_args(pimdb_t h, char *ws) {
     a.mixed = h->precision == PIMDB_MIXED;
     a.direct = h->precision == PIMDB_FP64_DIRECT;
     a.wait_ticks = h->wait_ticks;
+    a.help_rows = h->split_rows;
     return a;
 }
 

@@ -1324,13 +1324,15 @@ __device__ __forceinline__ bool helper_fetch(const LaunchArgs &a, const RecCtx &
     return true;
 }
 
-// Helper h of a split recursion: row j of wave w < W - 1 holds its block
-// b(j (W - 1) + w); the last wave fetches the published blocks one ahead of
-// the panels, so the wait and the loads overlap the arithmetic.
+// Helper h of a split recursion: row j of wave w < WR holds its block
+// b(j WR + w), with WR row waves chosen by the host (four, one per SIMD,
+// when the helper has a CU of its own; otherwise all but the last wave);
+// the last wave fetches the published blocks one ahead of the panels, so
+// the wait and the loads overlap the arithmetic.
 template <bool FWD, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool MAG>
 __device__ __forceinline__ void helper_rows(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c, int h) {
     const int t = c.t, w = t >> 6, lane = t & 63, nblk = c.nblk, H = sd.nhelp;
-    const int WR = c.W - 1; // row waves
+    const int WR = min(c.W - 1, a.help_rows); // row waves
     int b0, nown;
     helper_blocks(FWD, nblk, H, h, b0, nown);
     if (nown == 0) return;
@@ -1359,7 +1361,8 @@ __device__ __forceinline__ void helper_rows(const LaunchArgs &a, const SysDesc &
         *cnt = 0;
     }
     __syncthreads();
-    if (w == WR && !helper_fetch<FWD, BOX, MIXED>(a, c, X, i_begin, urgent_block(i_begin), 0) && lane == 0)
+    const int wf = c.W - 1; // the fetch wave; waves WR .. wf-1 only keep the barriers
+    if (w == wf && !helper_fetch<FWD, BOX, MIXED>(a, c, X, i_begin, urgent_block(i_begin), 0) && lane == 0)
         *abort_flag = 1;
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -1368,11 +1371,11 @@ __device__ __forceinline__ void helper_rows(const LaunchArgs &a, const SysDesc &
         if (*abort_flag) return;
         const int ub = urgent_block(i);
         if (ub >= 0) ++nurg;
-        if (w == WR) {
+        if (w == wf) {
             if (i != i_end && !helper_fetch<FWD, BOX, MIXED>(a, c, X, i + di, urgent_block(i + di), (it + 1) & 1) &&
                 lane == 0)
                 *abort_flag = 1;
-        } else {
+        } else if (w < WR) {
             if (ub >= 0) { // this wave's slice of block i's terms for the urgent row
                 const double *D = c.sm + L_UR + (it & 1) * 4 * BK + lane;
                 Rows<1> U;
@@ -1529,7 +1532,8 @@ __device__ __forceinline__ void recursion_role(const LaunchArgs &a, const SysDes
         if (sd.nhelp > 0) {
             int b0, nown;
             helper_blocks(FWD, c.nblk, sd.nhelp, helper, b0, nown);
-            const int jj = max(1, (nown + c.W - 2) / (c.W - 1)); // rows on the W - 1 row waves
+            const int wr = min(c.W - 1, a.help_rows);
+            const int jj = max(1, (nown + wr - 1) / wr); // rows on the row waves
             help_dispatch<1, J, FWD, BOX, MIXED, WSUM>(a, sd, c, helper, jj, wrap_ok);
             return;
         }

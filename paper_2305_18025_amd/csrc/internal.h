@@ -118,7 +118,7 @@ struct LaunchArgs {
     int32_t mode;
     int32_t mixed;         // 1: FP32 compensated endpoint spring lengths
     int32_t direct;        // 1: direct-form pair lengths for open boundaries (host-side choice of variant)
-    int32_t pad;
+    int32_t help_rows;     // split recursions: row waves per helper workgroup
     uint64_t wait_ticks;   // time limit of a split recursion's wait, 100 MHz clock ticks
 };
 

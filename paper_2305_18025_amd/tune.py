@@ -42,7 +42,7 @@ def cache_key(eng) -> str:
     return "N%d_S%d_%s_%s" % (_bucket(max(eng.N)), _bucket(eng.S), eng.precision, "box" if eng.box > 0 else "open")
 
 
-SPLITS = (7, 14, 28, 56)  # blocks per helper tried for split recursions
+SPLITS = (4, 7, 14, 28, 56)  # blocks per helper tried for split recursions
 
 
 def candidates(nmax: int, S: int = 1):
