@@ -22,6 +22,8 @@ namespace {
 
 constexpr int BV = 32;  // v-block of the derivative recurrence
 constexpr int SOLVE_T = 256; // threads of the recurrence kernel, one bead coordinate each
+constexpr int AST = 66;      // LDS row stride (doubles) of a wave's streamed sums: 64 + 2 against bank conflicts
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double mi(double d, double box, double ib) {
     return box > 0.0 ? fma(-box, rint(d * ib), d) : d;
@@ -323,8 +325,9 @@ __global__ void k_orig_prefix(OrigArgs a) {
 // their sum is cA C[l-1][v-1] + cB W[l-1][v-1]; the last bead at v = l
 // (closing spring to bead 1 of u) is the sum T.  The rest, the terms
 // u-1 = g >= l, is a lower-triangular recurrence over g in blocks of BV
-// values of v: the G values of earlier blocks are streamed through once per
-// block against a tile of W in LDS; the block's own triangle follows.
+// values of v: the terms of earlier blocks' G values form a dense product
+// (a tile of W^T in LDS times the wave's G values) on the FP64 matrix
+// cores; the block's own triangle follows, one lane per right-hand side.
 __global__ void __launch_bounds__(SOLVE_T) k_orig_solve(OrigArgs a) {
     const int N = a.N, P = a.P, t = threadIdx.x;
     const int64_t NB = (int64_t)3 * P * N;
@@ -339,8 +342,16 @@ __global__ void __launch_bounds__(SOLVE_T) k_orig_solve(OrigArgs a) {
     const double *W = a.ws + OrigLayout::W(N), *C = a.ws + OrigLayout::C(N), *T = a.ws + OrigLayout::T(N);
     // this workgroup's history: [v-1][t], SOLVE_T per row
     double *G = a.ws + OrigLayout::G(N) + (size_t)blockIdx.x * N * SOLVE_T;
-    __shared__ double tile[BV][BV]; // W[g][v-1], g in the chunk, v in the block
-    __shared__ double dt[BV][BV];   // W[g][v-1], g and v in the block
+    __shared__ double tile[BV][BV + 1]; // W[g][v-1], g in the chunk, v in the block
+    __shared__ double dt[BV][BV];       // W[g][v-1], g and v in the block
+    __shared__ double accs[SOLVE_T / 64 * BV * AST]; // each wave's streamed sums, [v][b]
+    const int w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+    int lb[4]; // particles (1-based) of this lane's B columns
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int64_t bq = (int64_t)blockIdx.x * SOLVE_T + 64 * w + 16 * nt + li;
+        lb[nt] = (int)((bq < NB ? bq : NB - 1) / (3 * P)) + 1;
+    }
     const double box = a.box, ib = a.inv_box, mw2 = a.mw2;
     // dE/dx_b = m w^2 ((x - prev) + (x - next)) for the cycles that contain l
     const double x0 = bead(a, j, c, lz);
@@ -364,21 +375,30 @@ __global__ void __launch_bounds__(SOLVE_T) k_orig_solve(OrigArgs a) {
     const double *Cl = C + (size_t)lz * N; // C[l-1][v-1]
     double last = 0.0;
     for (int v0 = ((lmin1 - 1) / BV) * BV + 1; v0 <= N; v0 += BV) {
-        double acc[BV];
+        // rows g in [lmin1, v0) in chunks of BV on the matrix cores: for this
+        // wave's 64 right-hand sides (4 column tiles of 16) and the block's
+        // 32 values of v (2 row tiles), D[v][b] += W^T[v][g] G[g][b], 4 g per
+        // v_mfma_f64_16x16x4f64 (A: lane l holds A[l%16][l/16]; B: lane l
+        // holds B[l/16][l%16]; D: lane l, element r holds D[4r + l/16][l%16])
+        d4 D[2][4];
 #pragma unroll
-        for (int i = 0; i < BV; ++i) acc[i] = 0.0;
-        // rows g in [lmin1, v0) in chunks of BV: a tile of W in LDS, read
-        // by every lane (broadcast), against this lane's G values
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) D[mt][nt] = d4{0.0, 0.0, 0.0, 0.0};
         for (int gc = lmin1; gc < v0; gc += BV) {
-            // this lane's G values of the chunk, loaded together (rows before
-            // its particle, or past the chunk, read row 1 and count zero)
-            double xs[BV];
+            // this lane's B values of the chunk (rows before the column's
+            // particle, or past the chunk, read row 1 and count zero), loaded
+            // while the W tile is staged
+            double bv[BV / 4][4];
 #pragma unroll
-            for (int r = 0; r < BV; ++r) {
-                const int g = gc + r;
-                const bool use = g < v0 && g >= l1;
-                const double x = G[(size_t)((use ? g : 1) - 1) * SOLVE_T + t];
-                xs[r] = use ? x : 0.0;
+            for (int kk = 0; kk < BV / 4; ++kk) {
+                const int g = gc + 4 * kk + lk;
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    const bool use = g < v0 && g >= lb[nt];
+                    const double x = G[(size_t)((use ? g : 1) - 1) * SOLVE_T + 64 * w + 16 * nt + li];
+                    bv[kk][nt] = use ? x : 0.0;
+                }
             }
             __syncthreads();
             for (int e = t; e < BV * BV; e += SOLVE_T) {
@@ -388,11 +408,30 @@ __global__ void __launch_bounds__(SOLVE_T) k_orig_solve(OrigArgs a) {
             }
             __syncthreads();
 #pragma unroll
-            for (int r = 0; r < BV; ++r) {
+            for (int kk = 0; kk < BV / 4; ++kk) {
+                double av[2];
 #pragma unroll
-                for (int i = 0; i < BV; ++i) acc[i] = fma(tile[r][i], xs[r], acc[i]);
+                for (int mt = 0; mt < 2; ++mt) av[mt] = tile[4 * kk + lk][16 * mt + li];
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt)
+                        D[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], bv[kk][nt], D[mt][nt], 0, 0, 0);
             }
         }
+        // to one lane per right-hand side, through this wave's LDS rows
+        double *aw = accs + (size_t)w * BV * AST;
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) aw[(16 * mt + 4 * r + lk) * AST + 16 * nt + li] = D[mt][nt][r];
+        double acc[BV];
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int i = 0; i < BV; ++i) acc[i] = aw[i * AST + lane];
         __syncthreads();
         for (int e = t; e < BV * BV; e += SOLVE_T) {
             const int r = e / BV, i = e - r * BV;
