@@ -25,6 +25,7 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a) {
     const SysDesc sd = a.sys[it.sys];
     const int N = sd.N, P = sd.P, t = threadIdx.x, T = blockDim.x;
     const int64_t off = a.offs ? a.offs[it.sys] : sd.off;
+    if (off < 0) return; // a skipped system of the caller-packed batch
     const size_t NN = (size_t)N;
     const double *X = a.pos + off + (size_t)it.j * 3 * NN; // slice j: x[N], y[N], z[N]
     const int i = it.i0 + t;
@@ -78,6 +79,7 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a) {
 // Energy of each system: its items' partials in item order.
 __global__ void __launch_bounds__(64) k_pair_energy(PairArgs a) {
     const int s = blockIdx.x, t = threadIdx.x;
+    if (a.offs && a.offs[s] < 0) return; // skipped: its energy is not written
     const int b0 = a.beg[s], b1 = a.beg[s + 1];
     double v = 0.0;
     for (int b = b0 + t; b < b1; b += 64) v += a.epart[b];

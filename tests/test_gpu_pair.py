@@ -111,6 +111,17 @@ def test_pair_added_to_exchange_everywhere():
     for e in (eng, ref, orig):
         assert e.status() == 0
     assert torch.equal(E_only, E) and torch.equal(Eb, E) and torch.equal(Fb, F)
+    # a negative caller offset skips its system in the pair launch as well
+    offs2 = offs.clone()
+    offs2[1] = -1
+    Fb.fill_(5.0)
+    Eb.fill_(123.0)
+    eng.forces_batched(pos, offs2, Fb, Eb)
+    torch.cuda.synchronize()
+    assert eng.status() == 4  # PIMDB_STATUS_RANGE
+    assert float(Eb[1]) == 123.0 and float(Eb[0]) == float(E[0]) and float(Eb[2]) == float(E[2])
+    o1 = eng.offsets[1]
+    assert bool((Fb[o1:o1 + 3 * systems[1].P * systems[1].N] == 5.0).all())
     for i, s in enumerate(systems):
         Ep, Fp = pair_gaussian(s.R, G, SIG)
         for (Fx, Ex, Fy, Ey) in [(F, E, F0, E0), (Fd, Ed, Fd0, Ed0), (Fo, Eo, F0, E0)]:
