@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 output for the profiles/ directory.
 
-    python -m paper_2305_18025_amd.profiling stats <kernel_stats.csv> <out.md> "<command>"
+    python -m paper_2305_18025_amd.profiling stats <kernel_stats.csv> <out.md> "<command>" ["<note>"]
     python -m paper_2305_18025_amd.profiling traffic <fetch_counter.csv> <write_counter.csv> \
         <kernel substring> <batch> <copy bytes> <out.json> <out.md> "<command>"
 
@@ -51,13 +51,15 @@ def kernel_stats(csv_path):
     return out
 
 
-def stats_markdown(csv_path, out_md, command):
+def stats_markdown(csv_path, out_md, command, note=""):
     ks = kernel_stats(csv_path)
     lines = ["# rocprofv3 kernel statistics", "", "Command:", "", "```", command, "```", "",
              "| kernel | calls | avg (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|"]
     for k in ks:
         lines.append("| `%s` | %d | %.1f | %.1f | %.1f | %.1f%% |" % (
             k["name"], k["calls"], k["avg_ns"] / 1e3, k["min_ns"] / 1e3, k["max_ns"] / 1e3, k["pct"]))
+    if note:
+        lines += ["", note]
     open(out_md, "w").write("\n".join(lines) + "\n")
     return ks
 
@@ -142,7 +144,7 @@ def sq_summary(csv_path, substr, terms, out_md, command):
 
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
-        stats_markdown(sys.argv[2], sys.argv[3], sys.argv[4])
+        stats_markdown(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5] if len(sys.argv) > 5 else "")
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), int(sys.argv[6]), sys.argv[7], sys.argv[8],
                 sys.argv[9])
