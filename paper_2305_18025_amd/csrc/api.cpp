@@ -193,6 +193,9 @@ constexpr int SPLIT_T = 512;
 // A helper's row waves: one per SIMD when every workgroup has a CU of its
 // own (launch mode 2), all but the fetch wave when two share a CU (mode 1).
 int split_rows(int mode) { return mode == 2 ? 4 : SPLIT_T / 64 - 1; }
+// Threads of a split launch's workgroups: 1024 when each has a CU of its own
+// (a chain's phase A on 16 waves), else 512 (two per CU).
+int split_threads(int mode) { return mode == 2 ? 2 * SPLIT_T : SPLIT_T; }
 
 struct SplitPlan {
     int per = 1;
@@ -200,6 +203,7 @@ struct SplitPlan {
     int recursion_wgs = 0;
     int mode = 1;    // 2: one workgroup per CU (the plan fits), 1: two per CU
     int rows = 7;    // a helper's row waves
+    int threads = 512;
     std::vector<int> nhelp;
 };
 
@@ -232,16 +236,17 @@ bool plan_split(pimdb_t h, int g, SplitPlan &p) {
                 const int own = (nblk - 2 + nh - 1) / nh;
                 p.per = std::max(p.per, (own + rows - 1) / rows);
             } else {
-                p.per = std::max(p.per, (int)((h->N[s] + SPLIT_T - 1) / SPLIT_T));
+                p.per = std::max(p.per, (int)((h->N[s] + split_threads(mode) - 1) / split_threads(mode)));
             }
             p.helpers += 2 * nh;
             p.recursion_wgs += 2 + 2 * nh;
         }
         if (p.per > 2 || p.helpers == 0) continue;
-        const int occ = exchange_occupancy(box, mixed, SPLIT_T, p.per, mode);
+        const int occ = exchange_occupancy(box, mixed, split_threads(mode), p.per, mode);
         if (occ > 0 && (int64_t)p.recursion_wgs <= (int64_t)occ * h->cus) {
             p.mode = mode;
             p.rows = rows;
+            p.threads = split_threads(mode);
             return true;
         }
     }
@@ -309,7 +314,7 @@ int build_tables(pimdb_t h) {
     h->split_mode = h->split_g > 0 ? plan.mode : 0;
     h->split_rows = h->split_g > 0 ? plan.rows : 0;
     if (h->split_g > 0) {
-        h->threads = SPLIT_T;
+        h->threads = plan.threads;
         h->per_thread = plan.per;
     } else if (h->user_threads) {
         h->threads = h->user_threads;

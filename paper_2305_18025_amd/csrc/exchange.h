@@ -1678,6 +1678,14 @@ __global__ void __launch_bounds__(512, 4) k_exchange_split(LaunchArgs a) {
     exchange_body<J, BOX, MIXED, true>(a);
 }
 
+// Split launches whose workgroups each have a CU of their own: 1024 threads,
+// so a chain's phase A (the triangle's exponentials, the previous block's
+// terms) is spread over 16 waves.
+template <int J, bool BOX, bool MIXED>
+__global__ void __launch_bounds__(1024) k_exchange_split_wide(LaunchArgs a) {
+    exchange_body<J, BOX, MIXED, true>(a);
+}
+
 // LDS of one fused workgroup: the recursion regions, or the springs role's
 // reduction scratch (whichever is larger).  `exclusive`: more than half of a
 // CU's 160 KiB, so that each workgroup has a CU to itself (split launches

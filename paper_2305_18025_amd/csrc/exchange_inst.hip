@@ -21,8 +21,12 @@ hipError_t launch_exchange_variant(const LaunchArgs &a, int nitems, int threads,
     const size_t smem = exchange_smem_bytes(threads, split == 2);
     if constexpr (J <= 2) {
         if (split) {
-            if (threads > 512) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_exchange_split<J, BOX, MIXED>), dim3(nitems), dim3(threads), smem, st, a);
+            if (threads == 1024 && split == 2)
+                hipLaunchKernelGGL((k_exchange_split_wide<J, BOX, MIXED>), dim3(nitems), dim3(threads), smem, st, a);
+            else if (threads <= 512)
+                hipLaunchKernelGGL((k_exchange_split<J, BOX, MIXED>), dim3(nitems), dim3(threads), smem, st, a);
+            else
+                return hipErrorInvalidValue;
         } else {
             hipLaunchKernelGGL((k_exchange<J, BOX, MIXED>), dim3(nitems), dim3(threads), smem, st, a);
         }
@@ -39,7 +43,9 @@ int exchange_variant_occupancy(int threads, int split) {
     int n = 0;
     hipError_t e;
     if constexpr (J <= 2) {
-        if (split)
+        if (split && threads == 1024 && split == 2)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_exchange_split_wide<J, BOX, MIXED>, threads, smem);
+        else if (split)
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_exchange_split<J, BOX, MIXED>, threads, smem);
         else
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_exchange<J, BOX, MIXED>, threads, smem);
