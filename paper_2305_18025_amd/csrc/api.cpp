@@ -182,13 +182,13 @@ void auto_tuning(int64_t Nmax, int S, int &threads, int &per) {
     }
 }
 
-// Split recursions (exchange.h): a system of nblk = ceil(N / 64) >= 3
-// blocks gets nhelp = ceil((nblk - 2) / g) helper workgroups per direction,
-// each owning at most g of the blocks 2 .. nblk-1 (forward; backward
-// mirrored) on its W - 1 = 7 row waves (rows per thread = ceil(owned / 7)
-// <= 2).  Systems of one or two blocks stay whole.  The launch uses the
-// 512-thread split kernel and must fit the workgroups the device holds at
-// once, since the chain and helpers of a system wait on each other.
+// Split recursions (exchange.h): with lag L (2 when two workgroups share a
+// CU, 3 when each has its own), a system of nblk = ceil(N / 64) > L blocks
+// gets nhelp = ceil((nblk - L) / g) helper workgroups per direction, each
+// owning at most g of the blocks L .. nblk-1 (forward; backward mirrored)
+// on its row waves (rows per thread <= 2).  Systems of at most L blocks
+// stay whole.  The launch must fit the workgroups the device holds at once,
+// since the chain and helpers of a system wait on each other.
 constexpr int SPLIT_T = 512;
 // A helper's row waves: one per SIMD when every workgroup has a CU of its
 // own (launch mode 2), all but the fetch wave when two share a CU (mode 1).
@@ -196,6 +196,10 @@ int split_rows(int mode) { return mode == 2 ? 4 : SPLIT_T / 64 - 1; }
 // Threads of a split launch's workgroups: 1024 when each has a CU of its own
 // (a chain's phase A on 16 waves), else 512 (two per CU).
 int split_threads(int mode) { return mode == 2 ? 2 * SPLIT_T : SPLIT_T; }
+// Blocks between a published block and the one a helper delivers from it:
+// 3 when each workgroup has a CU (the chain forms the terms of the two
+// blocks before its current one while the steps run), else 2.
+int split_lag(int mode) { return mode == 2 ? 3 : 2; }
 
 struct SplitPlan {
     int per = 1;
@@ -207,13 +211,13 @@ struct SplitPlan {
     std::vector<int> nhelp;
 };
 
-int helpers_for(int64_t N, int g, int rows) {
+int helpers_for(int64_t N, int g, int rows, int lag) {
     const int nblk = (int)((N + 63) / 64);
-    if (nblk < 3 || g < 1) return 0;
-    int nh = (nblk - 2 + g - 1) / g;
+    if (nblk <= lag || g < 1) return 0;
+    int nh = (nblk - lag + g - 1) / g;
     const int most = 2 * rows; // blocks a helper can hold with two rows per thread
-    nh = std::max(nh, (nblk - 2 + most - 1) / most);
-    return std::min(nh, nblk - 2);
+    nh = std::max(nh, (nblk - lag + most - 1) / most);
+    return std::min(nh, nblk - lag);
 }
 
 // The plan for g blocks per helper: a CU of its own for every chain and
@@ -223,17 +227,17 @@ bool plan_split(pimdb_t h, int g, SplitPlan &p) {
     const int S = h->S;
     const bool box = h->box > 0 || h->precision == PIMDB_FP64_DIRECT, mixed = h->precision == PIMDB_MIXED;
     for (int mode : {2, 1}) {
-        const int rows = split_rows(mode);
+        const int rows = split_rows(mode), lag = split_lag(mode);
         p.nhelp.assign(S, 0);
         p.per = 1;
         p.helpers = 0;
         p.recursion_wgs = 0;
         for (int s = 0; s < S; ++s) {
             const int nblk = (int)((h->N[s] + 63) / 64);
-            const int nh = helpers_for(h->N[s], g, rows);
+            const int nh = helpers_for(h->N[s], g, rows, lag);
             p.nhelp[s] = nh;
             if (nh > 0) {
-                const int own = (nblk - 2 + nh - 1) / nh;
+                const int own = (nblk - lag + nh - 1) / nh;
                 p.per = std::max(p.per, (own + rows - 1) / rows);
             } else {
                 p.per = std::max(p.per, (int)((h->N[s] + split_threads(mode) - 1) / split_threads(mode)));

@@ -91,6 +91,17 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     return r;
 }
 
+// Workgroup barrier ordering LDS alone: a wave's global stores still in
+// flight need not complete first (the recursion workgroups never read back
+// another wave's global stores within a launch: results go to the next
+// launch, exchange-area payloads to other workgroups behind their own
+// flags), so the stores of one phase overlap the next.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ void set_flag(int32_t *flags, int bits) {
     __hip_atomic_fetch_or(flags, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -136,6 +136,13 @@ constexpr int KTRI = BK * (BK + 1) / 2;
 //   [LDS_RED, +T)      block reduction scratch of the spring role (a
 //                      workgroup runs either a recursion or springs, so
 //                      this aliases the recursion regions)
+// The chain of a split recursion with a CU of its own also has:
+//   [L_KP2, +KTRI), [L_KN2, +BK*BK/2)  a second triangle buffer (the next
+//                      block's triangle is formed while the current one is
+//                      in use)
+//   [L_PROG, +1)       the chain's count of published steps and the slot
+//                      waves' count of finished slices of the older block
+//                      (two ints)
 constexpr int L_STG = 0;
 constexpr int STG = 10; // doubles per staged particle
 constexpr int BS = BK + 2;
@@ -152,13 +159,16 @@ constexpr int L_ABT = L_DL + 2 * L_DLS;          // abort flag (int) of a split 
 constexpr int L_UR = L_ABT + 1;                  // a helper's urgent row constants {px, py, pz, hl} x 64, twice
 constexpr int L_UC = L_UR + 2 * 4 * BK;          // a helper's slice counter (int)
 constexpr int L_END = L_UC + 1;
+constexpr int L_KP2 = L_END;
+constexpr int L_KN2 = L_KP2 + KTRI;
+constexpr int L_PROG = L_KN2 + BK * BK / 2;
+constexpr int L_END2 = L_PROG + 1;
 constexpr int LDS_RED = 0;
 
 __device__ __forceinline__ double *stg_block(double *sm, int b) { return sm + L_STG + ((b % 3) * BS + 1) * STG; }
 __device__ __forceinline__ double *zm_block(double *sm, int b) { return sm + L_ZM + (b % 3) * BS + 1; }
 __device__ __forceinline__ int *ze_block(double *sm, int b) { return (int *)(sm + L_ZE) + (b % 3) * BS + 1; }
 __device__ __forceinline__ double *zl_block(double *sm, int b) { return sm + L_ZL + (b % 3) * BS + 1; }
-__device__ __forceinline__ int *kn_base(double *sm) { return (int *)(sm + L_KN); }
 __device__ __forceinline__ int *pe_base(double *sm) { return (int *)(sm + L_PE); }
 
 // Packed triangle of the diagonal block: forward row i_s holds lanes
@@ -272,6 +282,8 @@ struct RecCtx {
     double kap, box, ib;
     double ox, oy, oz; // origin of the dot form (bead 1 of particle 0)
     int32_t *flags;    // status word
+    int kp, kn;        // LDS offsets (doubles) of the triangle buffer in use
+    int lag;           // split recursions: a helper delivers the block `lag` after the published one
 };
 
 // Staged data of one particle.
@@ -610,14 +622,19 @@ __device__ __forceinline__ void panel(Rows<JJ> &R, const RecCtx &c, int blk) {
 // and (63 - wr, 63 - c) for c < wr; work row 32 takes the diagonal entries
 // of rows 32..63.  (Coordinates of the forward triangle s <= q; the
 // backward one is its mirror image.)  Wave w takes work rows w, w + W, ...
+// (or, given w0 >= 0, work rows w0, w0 + ws, ...).
 template <bool FWD, bool BOX, bool MIXED>
-__device__ __forceinline__ void diag_terms(const RecCtx &c, int k) {
-    const int lane = c.t & 63, w = c.t >> 6;
+__device__ __forceinline__ void diag_terms(const RecCtx &c, int k, int w0 = -1, int ws = 0) {
+    const int lane = c.t & 63;
     const int nst = min(BK, c.N - k * BK);
     const double *S = stg_block(c.sm, k);
-    double *KP = c.sm + L_KP;
-    int *KN = kn_base(c.sm);
-    for (int wr = w; wr <= BK / 2; wr += c.W) {
+    double *KP = c.sm + c.kp;
+    int *KN = (int *)(c.sm + c.kn);
+    if (w0 < 0) {
+        w0 = c.t >> 6;
+        ws = c.W;
+    }
+    for (int wr = w0; wr <= BK / 2; wr += ws) {
         int r, q; // forward-triangle row (step) and column (accumulator)
         bool ok = true;
         if (wr < BK / 2) {
@@ -697,13 +714,11 @@ __device__ __forceinline__ Acc read_partial(const RecCtx &c, int slot) {
     return Acc{PA[0], PA[BK], PA[2 * BK], PA[3 * BK], pe_base(c.sm)[slot * BK + lane]};
 }
 
-// Phase A2 for block k: wave w < ns adds its slice of block prev's steps
-// for block k's accumulators (rows from the staged block k) into LDS slot w.
-template <bool FWD, bool BOX, bool MIXED, bool WSUM, bool MAG, bool ILP2 = false>
-__device__ __forceinline__ void diag_partial(const RecCtx &c, int k, int prev, int ns) {
-    const int lane = c.t & 63, w = c.t >> 6;
-    if (w >= ns) return;
-    const double *me = stg_block(c.sm, k) + STG * lane;
+// The row of accumulator 64 k + lane (from the staged block k) in the form
+// the terms use, with an empty accumulator.
+template <bool FWD, bool BOX, bool MIXED>
+__device__ __forceinline__ Rows<1> staged_row(const RecCtx &c, int k) {
+    const double *me = stg_block(c.sm, k) + STG * (c.t & 63);
     Rows<1> R;
     if (FWD) {
         R.px[0] = me[3];
@@ -718,6 +733,16 @@ __device__ __forceinline__ void diag_partial(const RecCtx &c, int k, int prev, i
     }
     if (!BOX && !MIXED) dot_row(c.kap, R.px[0], R.py[0], R.pz[0], R.hl[0], R.px[0], R.py[0], R.pz[0], R.hl[0]);
     R.a[0] = Acc{0.0, 0.0, 0.0, 0.0, EMIN};
+    return R;
+}
+
+// Phase A2 for block k: wave w < ns adds its slice of block prev's steps
+// for block k's accumulators (rows from the staged block k) into LDS slot w.
+template <bool FWD, bool BOX, bool MIXED, bool WSUM, bool MAG, bool ILP2 = false>
+__device__ __forceinline__ void diag_partial(const RecCtx &c, int k, int prev, int ns) {
+    const int w = c.t >> 6;
+    if (w >= ns) return;
+    Rows<1> R = staged_row<FWD, BOX, MIXED>(c, k);
     const int nst = min(BK, c.N - prev * BK); // previous block: full except the backward top
     slice_sum<FWD, BOX, MIXED, WSUM, MAG, ILP2>(R, c, prev, (nst * w) / ns, (nst * (w + 1)) / ns);
     write_partial(c, w, R.a[0]);
@@ -727,26 +752,100 @@ __device__ __forceinline__ void diag_partial(const RecCtx &c, int k, int prev, i
 // serially on row j (lane i: accumulator 64 k + i).  Afterwards every lane's
 // row is final: its published value goes to the broadcast ring for the
 // panels and its results to global memory.
-template <bool FWD, int j, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR>
+// PROG: the broadcast ring's values go out every eight steps (each lane's
+// current value; those of the lanes already final are what the ring
+// needs), followed by the count of steps done, pbase + steps, in the LDS
+// word *prog; the log2 form of the ring is then left to its readers.
+template <bool FWD, int j, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool PROG = false>
 __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bool has_prev, double *zm_out,
-                                         double *ze_out, double *r_out, int ns) {
+                                         double *ze_out, double *r_out, int ns, int *prog = nullptr,
+                                         int pbase = 0) {
     const int lane = c.t & 63, q = k * BK + lane, N = c.N;
     const size_t NN = c.NN;
     const int nst = min(BK, N - k * BK);
     Acc &r = R.a[j];
     if (has_prev) {
-        for (int w = 0; w < ns; ++w) {
-            const double *PA = c.sm + L_PA + w * 4 * BK + lane;
-            acc_merge<WSUM>(r, Acc{PA[0], PA[BK], PA[2 * BK], PA[3 * BK], pe_base(c.sm)[w * BK + lane]});
+        // the partial sums join in one pass: the largest reference first,
+        // then each sum rescaled to it and added in slot order (the same
+        // sums as merging them one by one); when the partial sums all hold
+        // that reference they are added as they are.  The reads go in
+        // batches (all exponents, then four slots at a time) so that their
+        // latencies overlap; slots past ns are read (they lie inside the
+        // partial-sum region) but not used.
+        const int *PE = pe_base(c.sm) + lane;
+        int pe[KSPLIT];
+#pragma unroll
+        for (int w = 0; w < KSPLIT; ++w) pe[w] = PE[w * BK];
+        __builtin_amdgcn_sched_barrier(0);
+        int en = r.e;
+#pragma unroll
+        for (int w = 0; w < KSPLIT; ++w)
+            if (w < ns) en = max(en, pe[w]);
+        bool same = true;
+#pragma unroll
+        for (int w = 0; w < KSPLIT; ++w)
+            if (w < ns) same &= pe[w] == en;
+        const bool one_ref = __builtin_amdgcn_ballot_w64(!same) == 0;
+        const int a0 = sub_sat(r.e, en);
+        r.A = ldexp(r.A, a0);
+        if (WSUM) {
+            r.Wx = ldexp(r.Wx, a0);
+            r.Wy = ldexp(r.Wy, a0);
+            r.Wz = ldexp(r.Wz, a0);
         }
+#pragma unroll
+        for (int h = 0; h < KSPLIT; h += 4) {
+            double pa[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double *PA = c.sm + L_PA + (h + u) * 4 * BK + lane;
+                pa[u][0] = PA[0];
+                if (WSUM) {
+                    pa[u][1] = PA[BK];
+                    pa[u][2] = PA[2 * BK];
+                    pa[u][3] = PA[3 * BK];
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (h + u < ns) {
+                    const int b = one_ref ? 0 : sub_sat(pe[h + u], en);
+                    r.A += ldexp(pa[u][0], b);
+                    if (WSUM) {
+                        r.Wx += ldexp(pa[u][1], b);
+                        r.Wy += ldexp(pa[u][2], b);
+                        r.Wz += ldexp(pa[u][3], b);
+                    }
+                }
+            }
+        }
+        r.e = en;
     }
     const double ivd = FWD ? 1.0 / (double)(q + 1) : (q > 0 ? 1.0 / (double)q : 0.0);
     const double *S = stg_block(c.sm, k);
-    const double *KPl = c.sm + L_KP + lane;
-    const int *KNl = kn_base(c.sm) + lane;
+    const double *KPl = c.sm + c.kp + lane;
+    const int *KNl = (const int *)(c.sm + c.kn) + lane;
     const int first = FWD ? 0 : nst - 1;
     double zm = zm_block(c.sm, k)[first];
     int ze = ze_block(c.sm, k)[first];
+    // PROG: this lane's ring entry (the step that reads its value), if any
+    const int psp = FWD ? q + 1 : q - 1;
+    const bool pown = PROG && q < N && psp >= 0 && psp < N;
+    double *pzm = PROG ? zm_block(c.sm, max(psp, 0) / BK) + max(psp, 0) % BK : nullptr;
+    int *pze = PROG ? ze_block(c.sm, max(psp, 0) / BK) + max(psp, 0) % BK : nullptr;
+    double lmz = 0.0; // this lane's current value (mantissa, exponent)
+    int lez = 0;
+    auto publish = [&](int done) {
+        if (pown) {
+            *pzm = lmz;
+            *pze = lez;
+        }
+        // LDS requests of a wave complete in order: the values are in place
+        // before the count that announces them
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (lane == 0) __hip_atomic_store(prog, pbase + done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
     // One step: every lane adds the term of step is (lanes the step does not
     // reach read an EMASK exponent and add nothing; their KP reads stay
     // inside the zero-filled triangle), then the owner (lane is) is complete
@@ -773,8 +872,10 @@ __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bo
         if (__builtin_expect(__builtin_amdgcn_ballot_w64(kk > RENORM) != 0, 0)) kk = acc_shift<WSUM>(r, te);
         acc_add<WSUM>(r, zm * p, kk, dx, dy, dz);
         const double zz = r.A * ivd;
-        zm = readlane_f64(__builtin_amdgcn_frexp_mant(zz), is);
-        ze = __builtin_amdgcn_readlane(r.e + __builtin_amdgcn_frexp_exp(zz), is);
+        lmz = __builtin_amdgcn_frexp_mant(zz);
+        lez = r.e + __builtin_amdgcn_frexp_exp(zz);
+        zm = readlane_f64(lmz, is);
+        ze = __builtin_amdgcn_readlane(lez, is);
     };
     bool done = false;
     if constexpr (UNR) {
@@ -801,6 +902,9 @@ __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bo
                     es[nx] = KNl[is2 * BK];
                 }
                 step(is, ps[cu], es[cu], xs[cu], ys[cu], zs[cu]);
+                if constexpr (PROG) {
+                    if ((i & 7) == 7) publish(i + 1);
+                }
             }
             done = true;
         }
@@ -826,9 +930,11 @@ __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bo
         for (int i = 0; i < nst; i += 2) {
             db = fetch(i + 1);
             step(FWD ? i : nst - 1 - i, da.p, da.n, da.x, da.y, da.z);
+            if (PROG && ((i & 7) == 7 || i + 1 == nst)) publish(i + 1);
             if (i + 1 < nst) {
                 da = fetch(i + 2);
                 step(FWD ? i + 1 : nst - 2 - i, db.p, db.n, db.x, db.y, db.z);
+                if (PROG && ((i & 7) == 6 || i + 2 == nst)) publish(i + 2);
             }
         }
     }
@@ -841,7 +947,7 @@ __device__ __forceinline__ void diagonal(Rows<JJ> &R, const RecCtx &c, int k, bo
         // empty-accumulator sentinel, so the input is out of range
         if (__builtin_expect(ez > EZ_LIM || ez < -EZ_LIM, 0)) set_flag(c.flags, ST_RANGE);
         const int sp = FWD ? q + 1 : q - 1; // step that reads this value
-        if (sp >= 0 && sp < N) {
+        if (!PROG && sp >= 0 && sp < N) {
             const double *su = stg_block(c.sm, sp / BK) + STG * (sp % BK);
             zm_block(c.sm, sp / BK)[sp % BK] = mz;
             ze_block(c.sm, sp / BK)[sp % BK] = ez;
@@ -1004,8 +1110,8 @@ __device__ __forceinline__ void rec_prologue(const RecCtx &c, double *zm_out, do
             ze_out[N + 1] = 0.0;
         }
     }
-    for (int i = t; i < BK * BK; i += T) kn_base(c.sm)[i] = EMASK;
-    for (int i = t; i < KTRI; i += T) c.sm[L_KP + i] = 0.0;
+    for (int i = t; i < BK * BK; i += T) ((int *)(c.sm + c.kn))[i] = EMASK;
+    for (int i = t; i < KTRI; i += T) c.sm[c.kp + i] = 0.0;
     // loads of the rows are complete before the loop (a wait inside it would
     // also wait for the staging loads issued there)
     __builtin_amdgcn_s_waitcnt(0);
@@ -1040,7 +1146,7 @@ __device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDes
             __builtin_amdgcn_s_setprio(0);
         }
         if (stage) stage_store(c, nb, g);
-        __syncthreads();
+        lds_barrier();
         // phase B
         int x;
         bool dg;
@@ -1052,7 +1158,7 @@ __device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDes
             dg = x > 0 && (x - 1) * W + w == k;
         }
         wave_dispatch<FWD, 0, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, k, x, dg, zm_out, ze_out, r_out);
-        __syncthreads();
+        lds_barrier();
     }
     if (range_bad) set_flag(a.flags, ST_RANGE);
 }
@@ -1060,19 +1166,23 @@ __device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDes
 
 // ------------------------------------------------------- split recursions
 // For small batches one workgroup per recursion leaves most CUs idle, so a
-// system's recursion may be spread over 1 + H workgroups (nhelp = H):
-//  - the chain workgroup runs phase A of every block k (the triangle's
-//    exponentials; the previous block's terms for block k's accumulators)
-//    and the block's serial steps, and publishes the block's step values
-//    (what the panels use) to the exchange area;
-//  - helper h owns the accumulators of every H-th block from 2 + h up
-//    (forward; backward from nblk - 3 - h down).  For every published block
-//    i it adds block i's terms to its accumulators of blocks at least two
-//    blocks further in recursion order, and the accumulator of the block
-//    exactly two further then holds every term but those of the next block
-//    (which the chain adds in its phase A): it is delivered to the chain.
-// A delivery for block k is made while the chain runs block k - 1, so the
-// hand-over latency stays off the serial path.  Flags and payloads are
+// system's recursion may be spread over 1 + H workgroups (nhelp = H), with
+// a lag L (2, or 3 when every workgroup has a CU of its own):
+//  - the chain workgroup adds the terms of the L - 1 blocks before block k
+//    to block k's accumulators, forms the triangle's exponentials, runs the
+//    block's serial steps, and publishes the block's step values (what the
+//    panels use) to the exchange area;
+//  - helper h owns the accumulators of every H-th block from L + h up
+//    (forward; backward from nblk - 1 - L - h down).  For every published
+//    block i it adds block i's terms to its accumulators of blocks at least
+//    L blocks further in recursion order, and the accumulator of the block
+//    exactly L further then holds every term but those of the L - 1 blocks
+//    before it (which the chain adds): it is delivered to the chain.
+// A delivery for block k is made while the chain runs block k - L + 1 or
+// later, so the hand-over latency stays off the serial path.  With L = 2
+// the chain adds the previous block's terms before the block's steps
+// (chain_rows); with L = 3 all but the last factor of that work is done
+// while the previous block's steps run (chain_rows_wide).  Flags and payloads are
 // device-scope relaxed atomics, which bypass the caches that are not
 // coherent across the XCDs without flushing them; a producer waits for its
 // payload stores to complete before it stores the flag.  Every wait is
@@ -1105,6 +1215,21 @@ __device__ __forceinline__ bool wave_wait(const int *flag, int32_t *status, uint
         }
     }
     return true;
+}
+
+// A delivered accumulator {A, Wx, Wy, Wz} x 64 and its exponents, from the
+// exchange area into LDS (D): every load is issued before the first store,
+// so their latencies overlap (an atomic load is not moved past the stores
+// that follow it).
+__device__ __forceinline__ void fetch_delivery(double *D, const double *src, const int *esrc, int lane) {
+    const double a0 = ld_dev(src + lane), a1 = ld_dev(src + BK + lane), a2 = ld_dev(src + 2 * BK + lane),
+                 a3 = ld_dev(src + 3 * BK + lane);
+    const int e = ld_dev(esrc + lane);
+    D[lane] = a0;
+    D[BK + lane] = a1;
+    D[2 * BK + lane] = a2;
+    D[3 * BK + lane] = a3;
+    ((int *)(D + 4 * BK))[lane] = e;
 }
 
 // After the wave's payload stores: wait for them, then set the flag.
@@ -1169,7 +1294,7 @@ __device__ __forceinline__ void chain_rows(const LaunchArgs &a, const SysDesc &s
         }
         if (last && has_prev) wave_signal(X.pub_flag + prev); // its stores have completed by now
         if (last && nb >= 0 && nb < nblk) stage_store(c, nb, g);
-        __syncthreads();
+        lds_barrier();
         if (*abort_flag) return;
         if (w == 0) { // the serial steps, always on wave 0
             const double *me = stg_block(c.sm, k) + STG * lane;
@@ -1200,19 +1325,14 @@ __device__ __forceinline__ void chain_rows(const LaunchArgs &a, const SysDesc &s
             const int kn = FWD ? k + 1 : k - 1;
             if (FWD ? kn >= 2 : kn <= nblk - 3) {
                 if (wave_wait(X.del_flag + kn, a.flags, a.wait_ticks)) {
-                    double *D = c.sm + L_DL + ((it + 1) & 1) * L_DLS;
-                    const double *src = X.del_acc + (size_t)kn * 4 * BK + lane;
-                    D[lane] = ld_dev(src);
-                    D[BK + lane] = ld_dev(src + BK);
-                    D[2 * BK + lane] = ld_dev(src + 2 * BK);
-                    D[3 * BK + lane] = ld_dev(src + 3 * BK);
-                    ((int *)(D + 4 * BK))[lane] = ld_dev(X.del_e + (size_t)kn * BK + lane);
+                    fetch_delivery(c.sm + L_DL + ((it + 1) & 1) * L_DLS, X.del_acc + (size_t)kn * 4 * BK,
+                                   X.del_e + (size_t)kn * BK, lane);
                 } else if (lane == 0) {
                     *abort_flag = 1;
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
     if (w == W - 1) { // the last block (no helper needs it; published for completeness)
         const int kl = FWD ? nblk - 1 : 0;
@@ -1223,21 +1343,245 @@ __device__ __forceinline__ void chain_rows(const LaunchArgs &a, const SysDesc &s
     if (range_bad) set_flag(a.flags, ST_RANGE);
 }
 
-// Helper blocks, ascending: b(m) = b0 + m H for m < nown (forward b0 = 2 + h;
-// backward every H-th block from nblk - 3 - h down to the smallest, b0).
-__device__ __forceinline__ void helper_blocks(bool fwd, int nblk, int H, int h, int &b0, int &nown) {
+// log2 form of block blk's broadcast values for its steps n0 .. n1 - 1
+// (counted largest term first): log2 of the mantissa plus the step's own
+// exponent constant, one step per lane, into the LDS ring (what the panel
+// terms use).
+template <bool FWD, bool BOX, bool MIXED>
+__device__ __forceinline__ void ring_log2(const RecCtx &c, int blk, int n0, int n1) {
+    const int l = c.t & 63;
+    const int nst = min(BK, c.N - blk * BK);
+    if (n0 + l < n1) {
+        const int i = FWD ? nst - 1 - (n0 + l) : n0 + l;
+        zl_block(c.sm, blk)[i] =
+            log2_mant(zm_block(c.sm, blk)[i]) + step_const<FWD, !BOX && !MIXED>(stg_block(c.sm, blk) + STG * i);
+    }
+}
+
+// Chain workgroup of a split recursion with lag 3 and a CU of its own
+// (1024 threads, 16 waves; a second triangle buffer in LDS).  One barrier
+// per block: while wave 0 merges block k's partial sums and delivery and
+// runs its steps,
+//  - eight slot waves (none on wave 0's SIMD when waves go to SIMDs in
+//    turn) each form block k+1's partial sum over their slice of block
+//    k-1's steps (whose values are known) and of block k's: in the dot form
+//    the terms of block k's slice are formed first without their Z factor
+//    and multiplied in as wave 0 publishes the values, eight steps at a
+//    time; otherwise the whole terms follow the published values;
+//  - three waves form block k+1's triangle in the other buffer;
+//  - the last wave publishes block k-1's step values for the helpers,
+//    fetches block k+1's delivery and stages block k+2 (into the ring slot
+//    of block k-1 once the slot waves are done with it).
+// So the serial path carries the steps, the merge and one barrier.
+__device__ __forceinline__ int wide_slot(int w) { return ((w & 3) != 0 && w < 11) ? w - 1 - (w >> 2) : -1; }
+__device__ __forceinline__ int wide_tri(int w) { return w == 11 ? 0 : (w == 13 || w == 14 ? w - 12 : -1); }
+constexpr int WIDE_SLOTS = 8, WIDE_TRI = 3;
+constexpr int YC = BK / WIDE_SLOTS; // steps of a full slice
+
+// Spin (one wave) until the LDS word *cnt reaches target; bounded like
+// the waits between workgroups (ST_TIMEOUT after `ticks`, and the wave goes
+// on with whatever the word announces).
+__device__ __forceinline__ void lds_wait(const int *cnt, int target, int32_t *status, uint64_t ticks) {
+    const uint64_t t0 = wall_clock64();
+    while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) <
+           target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t0 > ticks) {
+            if ((threadIdx.x & 63) == 0) set_flag(status, ST_TIMEOUT);
+            break;
+        }
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+template <bool FWD, bool BOX, bool MIXED, bool WSUM>
+__device__ __forceinline__ void chain_rows_wide(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c) {
+    constexpr bool DOT = !BOX && !MIXED;
+    const int t = c.t, W = c.W, w = t >> 6, lane = t & 63, nblk = c.nblk, lag = c.lag;
+    const int sl = wide_slot(w), tr = wide_tri(w);
+    const bool last = w == W - 1;
+    double *zm_out, *ze_out, *r_out;
+    rec_outputs<FWD>(a, sd, zm_out, ze_out, r_out);
+    const XsPtrs X = xs_ptrs<FWD>(a, sd, nblk);
+    int *abort_flag = (int *)(c.sm + L_ABT);
+    int *prog = (int *)(c.sm + L_PROG), *xdone = prog + 1;
+    if (t == 0) {
+        *abort_flag = 0;
+        *prog = 0;
+        *xdone = 0;
+    }
+    bool range_bad = false;
+    RecCtx c2 = c; // the second triangle buffer
+    c2.kp = L_KP2;
+    c2.kn = L_KN2;
+    for (int i = t; i < BK * BK; i += c.T) ((int *)(c.sm + L_KN2))[i] = EMASK;
+    for (int i = t; i < KTRI; i += c.T) c.sm[L_KP2 + i] = 0.0;
+    const int first = FWD ? 0 : nblk - 1;
+    const int di = FWD ? 1 : -1;
+    Stage g{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (last) g = stage_load<BOX, MIXED>(c, first + di, range_bad);
+    rec_prologue<FWD, BOX, MIXED>(c, zm_out, ze_out, range_bad);
+    diag_terms<FWD, BOX, MIXED>(c, first);
+    if (last) stage_store(c, first + di, g);
+    lds_barrier();
+    for (int it = 0; it < nblk; ++it) {
+        const int k = first + di * it;
+        const int prev = k - di, nb = k + di, nn = k + 2 * di;
+        const bool has_prev = it > 0, has_nb = it + 1 < nblk;
+        const RecCtx &ck = (it & 1) ? c2 : c; // block k's triangle
+        const RecCtx &cn = (it & 1) ? c : c2; // block k+1's
+        if (w == 0) { // the serial steps
+            Rows<1> R = staged_row<FWD, BOX, MIXED>(c, k);
+            const bool delivered = FWD ? k >= lag : k <= nblk - 1 - lag;
+            if (delivered) {
+                const double *D = c.sm + L_DL + (it & 1) * L_DLS;
+                R.a[0] = Acc{D[lane], D[BK + lane], D[2 * BK + lane], D[3 * BK + lane], ((const int *)(D + 4 * BK))[lane]};
+            }
+            __builtin_amdgcn_s_setprio(2);
+            diagonal<FWD, 0, 1, BOX, MIXED, WSUM, true, true>(R, ck, k, has_prev, zm_out, ze_out, r_out, WIDE_SLOTS,
+                                                              prog, it * BK);
+            __builtin_amdgcn_s_setprio(0);
+            // wave 0 holds no staged data: assigned here, its registers
+            // are free during the steps
+            g = Stage{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        } else if (sl >= 0) {
+            if (has_nb) {
+                Rows<1> R = staged_row<FWD, BOX, MIXED>(c, nb);
+                if (has_prev) { // block k-1's terms (its values are known)
+                    const int np = min(BK, c.N - prev * BK);
+                    const int n0 = np - (np * (sl + 1)) / WIDE_SLOTS, n1 = np - (np * sl) / WIDE_SLOTS;
+                    ring_log2<FWD, BOX, MIXED>(c, prev, n0, n1);
+                    slice_sum<FWD, BOX, MIXED, WSUM, false, true>(R, c, prev, n0, n1);
+                }
+                // (its reads are issued before the count: LDS requests of a
+                // wave complete in order)
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                if (lane == 0) __hip_atomic_fetch_add(xdone, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                // block k's slice: chain positions [i0, i1), i.e. steps
+                // n0 .. n1 - 1 counted largest term first
+                const int nst = min(BK, c.N - k * BK);
+                const int i0 = (nst * sl) / WIDE_SLOTS, i1 = (nst * (sl + 1)) / WIDE_SLOTS;
+                const int n0 = nst - i1, n1 = nst - i0;
+                if (DOT) {
+                    if (i1 - i0 == YC) {
+                        const double *S = stg_block(c.sm, k);
+                        double yp[YC];
+                        int yn[YC];
+#pragma unroll
+                        for (int m = 0; m < YC; ++m) { // the terms without their Z factor, four at a time
+                            const int i = FWD ? i0 + m : nst - 1 - (i0 + m);
+                            double ux, uy, uz, uh;
+                            step_point<FWD, true>(S, i, ux, uy, uz, uh);
+                            exp2x(fma(R.px[0], ux, fma(R.py[0], uy, fma(R.pz[0], uz, R.hl[0] + uh))), yp[m], yn[m]);
+                            if (m == YC / 2 - 1) __builtin_amdgcn_sched_barrier(0);
+                        }
+                        lds_wait(prog, it * BK + i1, a.flags, a.wait_ticks);
+                        const double *Zm = zm_block(c.sm, k);
+                        const int *Ze = ze_block(c.sm, k);
+                        double zv[YC];
+                        int te[YC];
+                        int mx = 0;
+#pragma unroll
+                        for (int m = 0; m < YC; ++m) {
+                            const int i = FWD ? i0 + m : nst - 1 - (i0 + m);
+                            zv[m] = Zm[i];
+                            te[m] = Ze[i];
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int m = 0; m < YC; ++m) {
+                            te[m] = add_sat(yn[m], te[m]);
+                            mx = m == 0 ? te[0] : max(mx, te[m]);
+                        }
+                        // one reference move at most, for the slice's largest
+                        // term (moving it at the first such term gives the
+                        // same sums)
+                        Acc &r = R.a[0];
+                        if (__builtin_expect(__builtin_amdgcn_ballot_w64(sub_sat(mx, r.e) > RENORM) != 0, 0))
+                            acc_shift<WSUM>(r, mx);
+#pragma unroll
+                        for (int m = YC - 1; m >= 0; --m) { // largest term first
+                            const int i = FWD ? i0 + m : nst - 1 - (i0 + m);
+                            double ux, uy, uz, uh;
+                            step_point<FWD, true>(S, i, ux, uy, uz, uh);
+                            acc_add<WSUM>(r, yp[m] * zv[m], sub_sat(te[m], r.e), ux, uy, uz);
+                        }
+                    } else {
+                        lds_wait(prog, it * BK + max(i1, 1), a.flags, a.wait_ticks);
+                        ring_log2<FWD, BOX, MIXED>(c, k, n0, n1);
+                        slice_sum<FWD, BOX, MIXED, WSUM, false, false>(R, c, k, n0, n1);
+                    }
+                } else {
+                    lds_wait(prog, it * BK + max(i1, 1), a.flags, a.wait_ticks);
+                    ring_log2<FWD, BOX, MIXED>(c, k, n0, n1);
+                    slice_sum<FWD, BOX, MIXED, WSUM, false, true>(R, c, k, n0, n1);
+                }
+                write_partial(c, sl, R.a[0]);
+            } else if (lane == 0) {
+                __hip_atomic_fetch_add(xdone, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        } else {
+            if (last && has_prev) { // block k-1's step values for the helpers, first
+                const int np = min(BK, c.N - prev * BK);
+                const int i = lane < np ? lane : np - 1;
+                const double zl = log2_mant(zm_block(c.sm, prev)[i]) +
+                                  step_const<FWD, DOT>(stg_block(c.sm, prev) + STG * i);
+                st_dev(X.pub_zl + (size_t)prev * BK + lane, zl);
+                st_dev(X.pub_ze + (size_t)prev * BK + lane, ze_block(c.sm, prev)[lane]);
+            }
+            // block k+2's loads overlap the wait for the published stores
+            if (last && it + 2 < nblk) g = stage_load<BOX, MIXED>(c, nn, range_bad);
+            if (last && has_prev) wave_signal(X.pub_flag + prev);
+            if (last && has_nb) { // block k+1's delivery
+                const bool dl = FWD ? nb >= lag : nb <= nblk - 1 - lag;
+                if (dl) {
+                    if (wave_wait(X.del_flag + nb, a.flags, a.wait_ticks))
+                        fetch_delivery(c.sm + L_DL + ((it + 1) & 1) * L_DLS, X.del_acc + (size_t)nb * 4 * BK,
+                                       X.del_e + (size_t)nb * BK, lane);
+                    else if (lane == 0)
+                        *abort_flag = 1;
+                }
+            }
+            if (has_nb && tr >= 0) diag_terms<FWD, BOX, MIXED>(cn, nb, tr, WIDE_TRI);
+            if (last && it + 2 < nblk) {
+                // block k+2 goes to block k-1's ring slot once the slot
+                // waves have read block k-1
+                lds_wait(xdone, WIDE_SLOTS * (it + 1), a.flags, a.wait_ticks);
+                stage_store(c, nn, g);
+            }
+        }
+        lds_barrier();
+        if (*abort_flag) return;
+    }
+    if (last) { // the last block (no helper needs it; published for completeness)
+        const int kl = first + di * (nblk - 1);
+        const int np = min(BK, c.N - kl * BK);
+        const int i = lane < np ? lane : np - 1;
+        const double zl =
+            log2_mant(zm_block(c.sm, kl)[i]) + step_const<FWD, DOT>(stg_block(c.sm, kl) + STG * i);
+        st_dev(X.pub_zl + (size_t)kl * BK + lane, zl);
+        st_dev(X.pub_ze + (size_t)kl * BK + lane, ze_block(c.sm, kl)[lane]);
+        wave_signal(X.pub_flag + kl);
+    }
+    if (range_bad) set_flag(a.flags, ST_RANGE);
+}
+
+// Helper blocks, ascending: b(m) = b0 + m H for m < nown (forward b0 =
+// lag + h; backward every H-th block from nblk - 1 - lag - h down to the
+// smallest, b0).
+__device__ __forceinline__ void helper_blocks(bool fwd, int nblk, int H, int h, int lag, int &b0, int &nown) {
     if (fwd) {
-        b0 = 2 + h;
+        b0 = lag + h;
         nown = b0 < nblk ? (nblk - 1 - b0) / H + 1 : 0;
     } else {
-        const int top = nblk - 3 - h;
+        const int top = nblk - 1 - lag - h;
         b0 = top >= 0 ? top % H : 0;
         nown = top >= 0 ? (top - b0) / H + 1 : 0;
     }
 }
 
 // One wave's work on published block i: the panel over its live rows.
-// URG: this wave holds the block two further in recursion order (row LO
+// URG: this wave holds the block `lag` further in recursion order (row LO
 // forward, HI - 1 backward), whose terms of block i every row wave has
 // summed in slices (LDS slots 0 .. WR-1); once all slices are in, this wave
 // merges them into the row and delivers it, then runs its other rows.
@@ -1254,7 +1598,7 @@ __device__ __forceinline__ void helper_iter(Rows<JJ> &R, const RecCtx &c, int i,
             __builtin_amdgcn_s_sleep(1);
         Acc r = R.a[ju];
         for (int sl = 0; sl < nslices; ++sl) acc_merge<WSUM>(r, read_partial(c, sl));
-        const int b = FWD ? i + 2 : i - 2;
+        const int b = FWD ? i + c.lag : i - c.lag;
         double *dst = X.del_acc + (size_t)b * 4 * BK + lane;
         st_dev(dst, r.A);
         st_dev(dst + BK, r.Wx);
@@ -1318,8 +1662,10 @@ __device__ __forceinline__ bool helper_fetch(const LaunchArgs &a, const RecCtx &
         D[3 * BK] = U.hl[0];
     }
     if (!wave_wait(X.pub_flag + i, a.flags, a.wait_ticks)) return false;
-    zl_block(c.sm, i)[lane] = ld_dev(X.pub_zl + (size_t)i * BK + lane);
-    ze_block(c.sm, i)[lane] = ld_dev(X.pub_ze + (size_t)i * BK + lane);
+    const double zl = ld_dev(X.pub_zl + (size_t)i * BK + lane); // both loads before the stores
+    const int ze = ld_dev(X.pub_ze + (size_t)i * BK + lane);
+    zl_block(c.sm, i)[lane] = zl;
+    ze_block(c.sm, i)[lane] = ze;
     stage_store(c, i, g);
     return true;
 }
@@ -1333,8 +1679,9 @@ template <bool FWD, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool MAG>
 __device__ __forceinline__ void helper_rows(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c, int h) {
     const int t = c.t, w = t >> 6, lane = t & 63, nblk = c.nblk, H = sd.nhelp;
     const int WR = min(c.W - 1, a.help_rows); // row waves
+    const int lag = c.lag;
     int b0, nown;
-    helper_blocks(FWD, nblk, H, h, b0, nown);
+    helper_blocks(FWD, nblk, H, h, lag, b0, nown);
     if (nown == 0) return;
     const XsPtrs X = xs_ptrs<FWD>(a, sd, nblk);
     int *abort_flag = (int *)(c.sm + L_ABT);
@@ -1348,11 +1695,11 @@ __device__ __forceinline__ void helper_rows(const LaunchArgs &a, const SysDesc &
     // published blocks that some row still needs, in recursion order
     const int blast = b0 + (nown - 1) * H;
     const int i_begin = FWD ? 0 : nblk - 1;
-    const int i_end = FWD ? blast - 2 : b0 + 2; // inclusive
+    const int i_end = FWD ? blast - lag : b0 + lag; // inclusive
     const int di = FWD ? 1 : -1;
     // the block this helper delivers after block i (-1: none)
     auto urgent_block = [&](int i) {
-        const int ub = FWD ? i + 2 : i - 2;
+        const int ub = FWD ? i + lag : i - lag;
         return (ub >= b0 && ub <= blast && (ub - b0) % H == 0) ? ub : -1;
     };
     int *cnt = (int *)(c.sm + L_UC);
@@ -1390,12 +1737,12 @@ __device__ __forceinline__ void helper_rows(const LaunchArgs &a, const SysDesc &
             }
             int x;
             bool urg;
-            if (FWD) { // live: blocks >= i + 2, i.e. m >= m0
+            if (FWD) { // live: blocks >= i + lag, i.e. m >= m0
                 const int m0 = i <= h ? 0 : (i - h + H - 1) / H;
                 x = m0 <= w ? 0 : (m0 - w + WR - 1) / WR;
                 urg = ub >= 0 && x * WR + w == m0;
-            } else { // live: blocks <= i - 2, i.e. m < L
-                const int L = i - 2 >= b0 ? min((i - 2 - b0) / H + 1, nown) : 0;
+            } else { // live: blocks <= i - lag, i.e. m < L
+                const int L = i - lag >= b0 ? min((i - lag - b0) / H + 1, nown) : 0;
                 x = L - 1 >= w ? min((L - 1 - w) / WR + 1, JJ) : 0;
                 urg = ub >= 0 && x > 0 && (x - 1) * WR + w == L - 1;
             }
@@ -1405,7 +1752,7 @@ __device__ __forceinline__ void helper_rows(const LaunchArgs &a, const SysDesc &
                 __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
             helper_dispatch<FWD, 0, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, x, urg, X, WR, nurg * (WR - 1));
         }
-        __syncthreads();
+        lds_barrier();
     }
     if (range_bad) set_flag(a.flags, ST_RANGE);
 }
@@ -1488,8 +1835,9 @@ __device__ __forceinline__ void system_extent(const RecCtx &c, double &r1, doubl
 }
 
 // A recursion workgroup: the whole recursion (nhelp = 0), the chain of a
-// split recursion (helper < 0), or helper `helper` of one.
-template <int J, bool FWD, bool BOX, bool MIXED, bool WSUM, bool SPLIT>
+// split recursion (helper < 0), or helper `helper` of one.  WIDE: split
+// launches whose workgroups each have a CU (lag 3).
+template <int J, bool FWD, bool BOX, bool MIXED, bool WSUM, bool SPLIT, bool WIDE>
 __device__ __forceinline__ void recursion_role(const LaunchArgs &a, const SysDesc sd, double *sm, int helper) {
     RecCtx c;
     c.sm = sm;
@@ -1508,6 +1856,9 @@ __device__ __forceinline__ void recursion_role(const LaunchArgs &a, const SysDes
     c.oy = c.b1[c.NN];
     c.oz = c.b1[2 * c.NN];
     c.flags = a.flags;
+    c.kp = L_KP;
+    c.kn = L_KN;
+    c.lag = WIDE ? 3 : 2;
     // Range checks on the system's extent D (largest bead-P to bead-1
     // distance, at most the sum of the two radii about the origin; with
     // the minimum image at most sqrt(3) L / 2):
@@ -1526,12 +1877,15 @@ __device__ __forceinline__ void recursion_role(const LaunchArgs &a, const SysDes
     if (!BOX && !MIXED && c.t == 0 && -sd.kappa * fmax(r1, rP) > DOT_LIM) set_flag(a.flags, ST_PRECISION);
     if constexpr (SPLIT) {
         if (sd.nhelp > 0 && helper < 0) {
-            chain_rows<FWD, BOX, MIXED, WSUM>(a, sd, c);
+            if constexpr (WIDE)
+                chain_rows_wide<FWD, BOX, MIXED, WSUM>(a, sd, c);
+            else
+                chain_rows<FWD, BOX, MIXED, WSUM>(a, sd, c);
             return;
         }
         if (sd.nhelp > 0) {
             int b0, nown;
-            helper_blocks(FWD, c.nblk, sd.nhelp, helper, b0, nown);
+            helper_blocks(FWD, c.nblk, sd.nhelp, helper, c.lag, b0, nown);
             const int wr = min(c.W - 1, a.help_rows);
             const int jj = max(1, (nown + wr - 1) / wr); // rows on the row waves
             help_dispatch<1, J, FWD, BOX, MIXED, WSUM>(a, sd, c, helper, jj, wrap_ok);
@@ -1632,7 +1986,7 @@ __device__ __forceinline__ void springs_role(const LaunchArgs &a, const SysDesc 
 // the results of all workgroups are visible to it through the stream order
 // alone: no grid-wide flag, and no device-scope cache maintenance per
 // workgroup.
-template <int J, bool BOX, bool MIXED, bool SPLIT>
+template <int J, bool BOX, bool MIXED, bool SPLIT, bool WIDE = false>
 __device__ __forceinline__ void exchange_body(const LaunchArgs &a) {
     extern __shared__ double sm[];
     const Item it = a.items[blockIdx.x];
@@ -1647,11 +2001,11 @@ __device__ __forceinline__ void exchange_body(const LaunchArgs &a) {
     if (it.role == ROLE_FORWARD || it.role == ROLE_FHELP) {
         const int helper = it.role == ROLE_FHELP ? it.idx : -1;
         if (a.mode & M_WSUM)
-            recursion_role<J, true, BOX, MIXED, true, SPLIT>(a, sd, sm, helper);
+            recursion_role<J, true, BOX, MIXED, true, SPLIT, WIDE>(a, sd, sm, helper);
         else
-            recursion_role<J, true, BOX, MIXED, false, SPLIT>(a, sd, sm, helper);
+            recursion_role<J, true, BOX, MIXED, false, SPLIT, WIDE>(a, sd, sm, helper);
     } else if (it.role == ROLE_BACKWARD || it.role == ROLE_BHELP) {
-        recursion_role<J, false, BOX, MIXED, true, SPLIT>(a, sd, sm, it.role == ROLE_BHELP ? it.idx : -1);
+        recursion_role<J, false, BOX, MIXED, true, SPLIT, WIDE>(a, sd, sm, it.role == ROLE_BHELP ? it.idx : -1);
     } else {
         // 1024-thread kernels have 128 registers: smaller bead groups
         springs_role<BOX, (J >= 4 ? 8 : 4)>(a, sd, it.sys, it.idx, sm);
@@ -1678,23 +2032,24 @@ __global__ void __launch_bounds__(512, 4) k_exchange_split(LaunchArgs a) {
     exchange_body<J, BOX, MIXED, true>(a);
 }
 
-// Split launches whose workgroups each have a CU of their own: 1024 threads,
-// so a chain's phase A (the triangle's exponentials, the previous block's
-// terms) is spread over 16 waves.
+// Split launches whose workgroups each have a CU of their own: 1024 threads
+// and lag 3, so a chain's 16 waves form the next block's terms while its
+// wave 0 runs the current block's steps.
 template <int J, bool BOX, bool MIXED>
 __global__ void __launch_bounds__(1024) k_exchange_split_wide(LaunchArgs a) {
-    exchange_body<J, BOX, MIXED, true>(a);
+    exchange_body<J, BOX, MIXED, true, true>(a);
 }
 
 // LDS of one fused workgroup: the recursion regions, or the springs role's
-// reduction scratch (whichever is larger).  `exclusive`: more than half of a
-// CU's 160 KiB, so that each workgroup has a CU to itself (split launches
-// small enough for that: a chain or helper then shares no SIMD with
-// another workgroup's waves).
-constexpr size_t EXCLUSIVE_LDS = 96 * 1024;
+// reduction scratch (whichever is larger).  `exclusive` (split launches
+// whose workgroups each have a CU): the wide chain's regions as well, more
+// than half of a CU's 160 KiB, so that each workgroup has a CU to itself (a
+// chain or helper then shares no SIMD with another workgroup's waves).
 inline size_t exchange_smem_bytes(int threads, bool exclusive = false) {
-    const size_t b = (size_t)(threads > L_END ? threads : L_END) * sizeof(double);
-    return exclusive && b < EXCLUSIVE_LDS ? EXCLUSIVE_LDS : b;
+    const int n = exclusive ? L_END2 : L_END;
+    return (size_t)(threads > n ? threads : n) * sizeof(double);
 }
+static_assert(L_END2 * sizeof(double) <= 160 * 1024, "the wide chain's LDS exceeds a CU's");
+static_assert(L_END2 * sizeof(double) > 80 * 1024, "a wide split workgroup must hold its CU alone");
 
 } // namespace pimdb
