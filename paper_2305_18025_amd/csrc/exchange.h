@@ -1582,9 +1582,10 @@ __device__ __forceinline__ void helper_blocks(bool fwd, int nblk, int H, int h, 
 
 // One wave's work on published block i: the panel over its live rows.
 // URG: this wave holds the block `lag` further in recursion order (row LO
-// forward, HI - 1 backward), whose terms of block i every row wave has
-// summed in slices (LDS slots 0 .. WR-1); once all slices are in, this wave
-// merges them into the row and delivers it, then runs its other rows.
+// forward, HI - 1 backward), whose terms of block i the first nslices row
+// waves have summed in slices (LDS slots 0 .. nslices-1); once all slices
+// are in, this wave merges them into the row and delivers it, then runs its
+// other rows.
 template <bool FWD, int LO, int HI, bool URG, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool MAG>
 __device__ __forceinline__ void helper_iter(Rows<JJ> &R, const RecCtx &c, int i, const XsPtrs &X, int nslices,
                                             int target) {
@@ -1679,6 +1680,7 @@ template <bool FWD, int JJ, bool BOX, bool MIXED, bool WSUM, bool UNR, bool MAG>
 __device__ __forceinline__ void helper_rows(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c, int h) {
     const int t = c.t, w = t >> 6, lane = t & 63, nblk = c.nblk, H = sd.nhelp;
     const int WR = min(c.W - 1, a.help_rows); // row waves
+    const int nsl = min(WR, KSPLIT);          // of which the first nsl slice the urgent row (LDS slots)
     const int lag = c.lag;
     int b0, nown;
     helper_blocks(FWD, nblk, H, h, lag, b0, nown);
@@ -1723,7 +1725,7 @@ __device__ __forceinline__ void helper_rows(const LaunchArgs &a, const SysDesc &
                 lane == 0)
                 *abort_flag = 1;
         } else if (w < WR) {
-            if (ub >= 0) { // this wave's slice of block i's terms for the urgent row
+            if (ub >= 0 && w < nsl) { // this wave's slice of block i's terms for the urgent row
                 const double *D = c.sm + L_UR + (it & 1) * 4 * BK + lane;
                 Rows<1> U;
                 U.px[0] = D[0];
@@ -1732,7 +1734,7 @@ __device__ __forceinline__ void helper_rows(const LaunchArgs &a, const SysDesc &
                 U.hl[0] = D[3 * BK];
                 U.a[0] = Acc{0.0, 0.0, 0.0, 0.0, EMIN};
                 const int nst = min(BK, c.N - i * BK);
-                slice_sum<FWD, BOX, MIXED, WSUM, false, true>(U, c, i, (nst * w) / WR, (nst * (w + 1)) / WR);
+                slice_sum<FWD, BOX, MIXED, WSUM, false, true>(U, c, i, (nst * w) / nsl, (nst * (w + 1)) / nsl);
                 write_partial(c, w, U.a[0]);
             }
             int x;
@@ -1748,9 +1750,9 @@ __device__ __forceinline__ void helper_rows(const LaunchArgs &a, const SysDesc &
             }
             // count this wave's finished slice for the urgent row's owner (one
             // lane: a per-lane operand would be reduced by a scalar loop first)
-            if (ub >= 0 && !urg && lane == 0)
+            if (ub >= 0 && w < nsl && lane == 0)
                 __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-            helper_dispatch<FWD, 0, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, x, urg, X, WR, nurg * (WR - 1));
+            helper_dispatch<FWD, 0, JJ, BOX, MIXED, WSUM, UNR, MAG>(R, c, i, x, urg, X, nsl, nurg * nsl);
         }
         lds_barrier();
     }
