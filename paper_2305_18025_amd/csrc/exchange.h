@@ -131,7 +131,9 @@ constexpr int KTRI = BK * (BK + 1) / 2;
 //                      and the next block (split recursions' chain)
 //   [L_ABT, +1)        abort flag of a split recursion (int)
 //   [L_UR, +2*4*BK)    a helper's urgent-row constants for this and the
-//                      next iteration
+//                      next iteration; in a chain, its count of published
+//                      steps and the slot waves' count of finished slices
+//                      (L_PROG, two ints)
 //   [L_UC, +1)         a helper's count of finished urgent slices (int)
 //   [LDS_RED, +T)      block reduction scratch of the spring role (a
 //                      workgroup runs either a recursion or springs, so
@@ -140,9 +142,6 @@ constexpr int KTRI = BK * (BK + 1) / 2;
 //   [L_KP2, +KTRI), [L_KN2, +BK*BK/2)  a second triangle buffer (the next
 //                      block's triangle is formed while the current one is
 //                      in use)
-//   [L_PROG, +1)       the chain's count of published steps and the slot
-//                      waves' count of finished slices of the older block
-//                      (two ints)
 constexpr int L_STG = 0;
 constexpr int STG = 10; // doubles per staged particle
 constexpr int BS = BK + 2;
@@ -161,8 +160,8 @@ constexpr int L_UC = L_UR + 2 * 4 * BK;          // a helper's slice counter (in
 constexpr int L_END = L_UC + 1;
 constexpr int L_KP2 = L_END;
 constexpr int L_KN2 = L_KP2 + KTRI;
-constexpr int L_PROG = L_KN2 + BK * BK / 2;
-constexpr int L_END2 = L_PROG + 1;
+constexpr int L_END2 = L_KN2 + BK * BK / 2;
+constexpr int L_PROG = L_UR; // a chain's two counters (chains do not use the helpers' urgent rows)
 constexpr int LDS_RED = 0;
 
 __device__ __forceinline__ double *stg_block(double *sm, int b) { return sm + L_STG + ((b % 3) * BS + 1) * STG; }
@@ -1179,10 +1178,9 @@ __device__ __forceinline__ void recursion_rows(const LaunchArgs &a, const SysDes
 //    exactly L further then holds every term but those of the L - 1 blocks
 //    before it (which the chain adds): it is delivered to the chain.
 // A delivery for block k is made while the chain runs block k - L + 1 or
-// later, so the hand-over latency stays off the serial path.  With L = 2
-// the chain adds the previous block's terms before the block's steps
-// (chain_rows); with L = 3 all but the last factor of that work is done
-// while the previous block's steps run (chain_rows_wide).  Flags and payloads are
+// later, so the hand-over latency stays off the serial path.  The chain
+// forms the terms of the L - 1 blocks before block k while the steps of
+// block k-1 run (chain_rows_prog).  Flags and payloads are
 // device-scope relaxed atomics, which bypass the caches that are not
 // coherent across the XCDs without flushing them; a producer waits for its
 // payload stores to complete before it stores the flag.  Every wait is
@@ -1256,93 +1254,6 @@ __device__ __forceinline__ XsPtrs xs_ptrs(const LaunchArgs &a, const SysDesc &sd
                   fl + (2 * d) * nblk, fl + (2 * d + 1) * nblk};
 }
 
-// Chain workgroup of a split recursion (no accumulator rows of its own).
-template <bool FWD, bool BOX, bool MIXED, bool WSUM>
-__device__ __forceinline__ void chain_rows(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c) {
-    constexpr bool DOT = !BOX && !MIXED;
-    const int t = c.t, W = c.W, w = t >> 6, lane = t & 63, nblk = c.nblk;
-    double *zm_out, *ze_out, *r_out;
-    rec_outputs<FWD>(a, sd, zm_out, ze_out, r_out);
-    const XsPtrs X = xs_ptrs<FWD>(a, sd, nblk);
-    int *abort_flag = (int *)(c.sm + L_ABT);
-    if (t == 0) *abort_flag = 0;
-    bool range_bad = false;
-    rec_prologue<FWD, BOX, MIXED>(c, zm_out, ze_out, range_bad);
-    for (int it = 0; it < nblk; ++it) {
-        const int k = FWD ? it : nblk - 1 - it;
-        const int prev = FWD ? k - 1 : k + 1;
-        const bool has_prev = FWD ? k > 0 : k + 1 < nblk;
-        // blocks two or more steps into the recursion come with the sum of
-        // all but their previous block's terms from a helper
-        const bool delivered = FWD ? k >= 2 : k <= nblk - 3;
-        const int nb = FWD ? k + 1 : k - 1;
-        const bool last = w == W - 1;
-        // the last wave publishes the previous block's step values (from the
-        // LDS ring) for the helpers, stages the next block and shares the
-        // triangle; the other waves also take slices of the partial sums
-        Stage g{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        if (last && nb >= 0 && nb < nblk) g = stage_load<BOX, MIXED>(c, nb, range_bad);
-        if (last && has_prev) {
-            st_dev(X.pub_zl + (size_t)prev * BK + lane, zl_block(c.sm, prev)[lane]);
-            st_dev(X.pub_ze + (size_t)prev * BK + lane, ze_block(c.sm, prev)[lane]);
-        }
-        diag_terms<FWD, BOX, MIXED>(c, k);
-        if (has_prev) {
-            __builtin_amdgcn_s_setprio(1);
-            diag_partial<FWD, BOX, MIXED, WSUM, false, true>(c, k, prev, min(KSPLIT, W - 1));
-            __builtin_amdgcn_s_setprio(0);
-        }
-        if (last && has_prev) wave_signal(X.pub_flag + prev); // its stores have completed by now
-        if (last && nb >= 0 && nb < nblk) stage_store(c, nb, g);
-        lds_barrier();
-        if (*abort_flag) return;
-        if (w == 0) { // the serial steps, always on wave 0
-            const double *me = stg_block(c.sm, k) + STG * lane;
-            Rows<1> R;
-            if (FWD) {
-                R.px[0] = me[3];
-                R.py[0] = me[4];
-                R.pz[0] = me[5];
-                R.hl[0] = me[6];
-            } else {
-                R.px[0] = me[0];
-                R.py[0] = me[1];
-                R.pz[0] = me[2];
-                R.hl[0] = 0.0;
-            }
-            if (DOT) dot_row(c.kap, R.px[0], R.py[0], R.pz[0], R.hl[0], R.px[0], R.py[0], R.pz[0], R.hl[0]);
-            R.a[0] = Acc{0.0, 0.0, 0.0, 0.0, EMIN};
-            if (delivered) {
-                const double *D = c.sm + L_DL + (it & 1) * L_DLS;
-                R.a[0] = Acc{D[lane], D[BK + lane], D[2 * BK + lane], D[3 * BK + lane], ((const int *)(D + 4 * BK))[lane]};
-            }
-            __builtin_amdgcn_s_setprio(2);
-            diagonal<FWD, 0, 1, BOX, MIXED, WSUM, true>(R, c, k, has_prev, zm_out, ze_out, r_out,
-                                                         min(KSPLIT, W - 1));
-            __builtin_amdgcn_s_setprio(0);
-        } else if (last && it + 1 < nblk) {
-            // meanwhile the next block's delivery goes to the other LDS slot
-            const int kn = FWD ? k + 1 : k - 1;
-            if (FWD ? kn >= 2 : kn <= nblk - 3) {
-                if (wave_wait(X.del_flag + kn, a.flags, a.wait_ticks)) {
-                    fetch_delivery(c.sm + L_DL + ((it + 1) & 1) * L_DLS, X.del_acc + (size_t)kn * 4 * BK,
-                                   X.del_e + (size_t)kn * BK, lane);
-                } else if (lane == 0) {
-                    *abort_flag = 1;
-                }
-            }
-        }
-        lds_barrier();
-    }
-    if (w == W - 1) { // the last block (no helper needs it; published for completeness)
-        const int kl = FWD ? nblk - 1 : 0;
-        st_dev(X.pub_zl + (size_t)kl * BK + lane, zl_block(c.sm, kl)[lane]);
-        st_dev(X.pub_ze + (size_t)kl * BK + lane, ze_block(c.sm, kl)[lane]);
-        wave_signal(X.pub_flag + kl);
-    }
-    if (range_bad) set_flag(a.flags, ST_RANGE);
-}
-
 // log2 form of block blk's broadcast values for its steps n0 .. n1 - 1
 // (counted largest term first): log2 of the mantissa plus the step's own
 // exponent constant, one step per lane, into the LDS ring (what the panel
@@ -1358,24 +1269,33 @@ __device__ __forceinline__ void ring_log2(const RecCtx &c, int blk, int n0, int 
     }
 }
 
-// Chain workgroup of a split recursion with lag 3 and a CU of its own
-// (1024 threads, 16 waves; a second triangle buffer in LDS).  One barrier
-// per block: while wave 0 merges block k's partial sums and delivery and
+// Chain workgroup of a split recursion: 16 waves with a CU of its own and
+// lag 3 (DBUF: a second triangle buffer in LDS), or 8 waves sharing a CU
+// and lag 2.  While wave 0 merges block k's partial sums and delivery and
 // runs its steps,
-//  - eight slot waves (none on wave 0's SIMD when waves go to SIMDs in
-//    turn) each form block k+1's partial sum over their slice of block
-//    k-1's steps (whose values are known) and of block k's: in the dot form
-//    the terms of block k's slice are formed first without their Z factor
-//    and multiplied in as wave 0 publishes the values, eight steps at a
-//    time; otherwise the whole terms follow the published values;
-//  - three waves form block k+1's triangle in the other buffer;
+//  - slot waves (none on wave 0's SIMD when waves go to SIMDs in turn) each
+//    form block k+1's partial sum over their eighths of the block's steps:
+//    with lag 3 first the terms of block k-1's slice (its values are
+//    known); then, in the dot form, the terms of block k's slice without
+//    their Z factor, and, as wave 0 publishes the values (eight steps at a
+//    time), the products with them; otherwise the whole terms follow the
+//    published values;
+//  - with DBUF, three waves form block k+1's triangle in the other buffer
+//    (else all waves form it after the steps, before a second barrier);
 //  - the last wave publishes block k-1's step values for the helpers,
 //    fetches block k+1's delivery and stages block k+2 (into the ring slot
 //    of block k-1 once the slot waves are done with it).
-// So the serial path carries the steps, the merge and one barrier.
-__device__ __forceinline__ int wide_slot(int w) { return ((w & 3) != 0 && w < 11) ? w - 1 - (w >> 2) : -1; }
-__device__ __forceinline__ int wide_tri(int w) { return w == 11 ? 0 : (w == 13 || w == 14 ? w - 12 : -1); }
+// So the serial path carries the steps, the merge and one barrier (two
+// without DBUF).
 constexpr int WIDE_SLOTS = 8, WIDE_TRI = 3;
+// Slot waves (none on wave 0's SIMD when waves go to SIMDs in turn): the
+// first of the eight slices of wave w (-1: none); a slot wave takes every
+// fourth slice from there in 8-wave workgroups (one slice in 16-wave ones).
+__device__ __forceinline__ int prog_slot(int w, int W) {
+    if (W >= 16) return ((w & 3) != 0 && w < 11) ? w - 1 - (w >> 2) : -1;
+    return (w >= 1 && w <= 3) ? w - 1 : (w == 5 ? 3 : -1);
+}
+__device__ __forceinline__ int wide_tri(int w) { return w == 11 ? 0 : (w == 13 || w == 14 ? w - 12 : -1); }
 constexpr int YC = BK / WIDE_SLOTS; // steps of a full slice
 
 // Spin (one wave) until the LDS word *cnt reaches target; bounded like
@@ -1394,11 +1314,12 @@ __device__ __forceinline__ void lds_wait(const int *cnt, int target, int32_t *st
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-template <bool FWD, bool BOX, bool MIXED, bool WSUM>
-__device__ __forceinline__ void chain_rows_wide(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c) {
+template <bool FWD, bool BOX, bool MIXED, bool WSUM, bool DBUF>
+__device__ __forceinline__ void chain_rows_prog(const LaunchArgs &a, const SysDesc &sd, const RecCtx &c) {
     constexpr bool DOT = !BOX && !MIXED;
     const int t = c.t, W = c.W, w = t >> 6, lane = t & 63, nblk = c.nblk, lag = c.lag;
-    const int sl = wide_slot(w), tr = wide_tri(w);
+    constexpr int sls = DBUF ? WIDE_SLOTS : WIDE_SLOTS / 2; // slices per slot wave: one (DBUF) or two
+    const int sl0 = prog_slot(w, DBUF ? 16 : 8), tr = DBUF ? wide_tri(w) : -1;
     const bool last = w == W - 1;
     double *zm_out, *ze_out, *r_out;
     rec_outputs<FWD>(a, sd, zm_out, ze_out, r_out);
@@ -1411,11 +1332,13 @@ __device__ __forceinline__ void chain_rows_wide(const LaunchArgs &a, const SysDe
         *xdone = 0;
     }
     bool range_bad = false;
-    RecCtx c2 = c; // the second triangle buffer
-    c2.kp = L_KP2;
-    c2.kn = L_KN2;
-    for (int i = t; i < BK * BK; i += c.T) ((int *)(c.sm + L_KN2))[i] = EMASK;
-    for (int i = t; i < KTRI; i += c.T) c.sm[L_KP2 + i] = 0.0;
+    RecCtx c2 = c; // the second triangle buffer (DBUF)
+    if (DBUF) {
+        c2.kp = L_KP2;
+        c2.kn = L_KN2;
+        for (int i = t; i < BK * BK; i += c.T) ((int *)(c.sm + L_KN2))[i] = EMASK;
+        for (int i = t; i < KTRI; i += c.T) c.sm[L_KP2 + i] = 0.0;
+    }
     const int first = FWD ? 0 : nblk - 1;
     const int di = FWD ? 1 : -1;
     Stage g{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1428,8 +1351,12 @@ __device__ __forceinline__ void chain_rows_wide(const LaunchArgs &a, const SysDe
         const int k = first + di * it;
         const int prev = k - di, nb = k + di, nn = k + 2 * di;
         const bool has_prev = it > 0, has_nb = it + 1 < nblk;
-        const RecCtx &ck = (it & 1) ? c2 : c; // block k's triangle
-        const RecCtx &cn = (it & 1) ? c : c2; // block k+1's
+        const RecCtx &ck = (DBUF && (it & 1)) ? c2 : c; // block k's triangle
+        const RecCtx &cn = (DBUF && !(it & 1)) ? c2 : c; // block k+1's
+        if (!DBUF && it > 0) { // one buffer: block k's triangle once block k-1's steps are done
+            diag_terms<FWD, BOX, MIXED>(c, k);
+            lds_barrier();
+        }
         if (w == 0) { // the serial steps
             Rows<1> R = staged_row<FWD, BOX, MIXED>(c, k);
             const bool delivered = FWD ? k >= lag : k <= nblk - 1 - lag;
@@ -1444,79 +1371,86 @@ __device__ __forceinline__ void chain_rows_wide(const LaunchArgs &a, const SysDe
             // wave 0 holds no staged data: assigned here, its registers
             // are free during the steps
             g = Stage{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        } else if (sl >= 0) {
+        } else if (sl0 >= 0) {
             if (has_nb) {
-                Rows<1> R = staged_row<FWD, BOX, MIXED>(c, nb);
-                if (has_prev) { // block k-1's terms (its values are known)
-                    const int np = min(BK, c.N - prev * BK);
-                    const int n0 = np - (np * (sl + 1)) / WIDE_SLOTS, n1 = np - (np * sl) / WIDE_SLOTS;
-                    ring_log2<FWD, BOX, MIXED>(c, prev, n0, n1);
-                    slice_sum<FWD, BOX, MIXED, WSUM, false, true>(R, c, prev, n0, n1);
-                }
-                // (its reads are issued before the count: LDS requests of a
-                // wave complete in order)
-                __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                if (lane == 0) __hip_atomic_fetch_add(xdone, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                // block k's slice: chain positions [i0, i1), i.e. steps
-                // n0 .. n1 - 1 counted largest term first
-                const int nst = min(BK, c.N - k * BK);
-                const int i0 = (nst * sl) / WIDE_SLOTS, i1 = (nst * (sl + 1)) / WIDE_SLOTS;
-                const int n0 = nst - i1, n1 = nst - i0;
-                if (DOT) {
-                    if (i1 - i0 == YC) {
-                        const double *S = stg_block(c.sm, k);
-                        double yp[YC];
-                        int yn[YC];
 #pragma unroll
-                        for (int m = 0; m < YC; ++m) { // the terms without their Z factor, four at a time
-                            const int i = FWD ? i0 + m : nst - 1 - (i0 + m);
-                            double ux, uy, uz, uh;
-                            step_point<FWD, true>(S, i, ux, uy, uz, uh);
-                            exp2x(fma(R.px[0], ux, fma(R.py[0], uy, fma(R.pz[0], uz, R.hl[0] + uh))), yp[m], yn[m]);
-                            if (m == YC / 2 - 1) __builtin_amdgcn_sched_barrier(0);
-                        }
-                        lds_wait(prog, it * BK + i1, a.flags, a.wait_ticks);
-                        const double *Zm = zm_block(c.sm, k);
-                        const int *Ze = ze_block(c.sm, k);
-                        double zv[YC];
-                        int te[YC];
-                        int mx = 0;
+                for (int sx = 0; sx < WIDE_SLOTS / sls; ++sx) {
+                    const int sl = sl0 + sx * sls;
+                    Rows<1> R = staged_row<FWD, BOX, MIXED>(c, nb);
+                    if (lag >= 3 && has_prev) { // block k-1's terms (its values are known)
+                        const int np = min(BK, c.N - prev * BK);
+                        const int n0 = np - (np * (sl + 1)) / WIDE_SLOTS, n1 = np - (np * sl) / WIDE_SLOTS;
+                        ring_log2<FWD, BOX, MIXED>(c, prev, n0, n1);
+                        slice_sum<FWD, BOX, MIXED, WSUM, false, true>(R, c, prev, n0, n1);
+                    }
+                    if (sx + 1 == WIDE_SLOTS / sls) { // the wave's last slice
+                        // (its reads are issued before the count: LDS
+                        // requests of a wave complete in order)
+                        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                        if (lane == 0)
+                            __hip_atomic_fetch_add(xdone, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                    // block k's slice: chain positions [i0, i1), i.e. steps
+                    // n0 .. n1 - 1 counted largest term first
+                    const int nst = min(BK, c.N - k * BK);
+                    const int i0 = (nst * sl) / WIDE_SLOTS, i1 = (nst * (sl + 1)) / WIDE_SLOTS;
+                    const int n0 = nst - i1, n1 = nst - i0;
+                    if (DOT) {
+                        if (i1 - i0 == YC) {
+                            const double *S = stg_block(c.sm, k);
+                            double yp[YC];
+                            int yn[YC];
 #pragma unroll
-                        for (int m = 0; m < YC; ++m) {
-                            const int i = FWD ? i0 + m : nst - 1 - (i0 + m);
-                            zv[m] = Zm[i];
-                            te[m] = Ze[i];
-                        }
-                        __builtin_amdgcn_sched_barrier(0);
+                            for (int m = 0; m < YC; ++m) { // the terms without their Z factor, four at a time
+                                const int i = FWD ? i0 + m : nst - 1 - (i0 + m);
+                                double ux, uy, uz, uh;
+                                step_point<FWD, true>(S, i, ux, uy, uz, uh);
+                                exp2x(fma(R.px[0], ux, fma(R.py[0], uy, fma(R.pz[0], uz, R.hl[0] + uh))), yp[m], yn[m]);
+                                if (m == YC / 2 - 1) __builtin_amdgcn_sched_barrier(0);
+                            }
+                            lds_wait(prog, it * BK + i1, a.flags, a.wait_ticks);
+                            const double *Zm = zm_block(c.sm, k);
+                            const int *Ze = ze_block(c.sm, k);
+                            double zv[YC];
+                            int te[YC];
+                            int mx = 0;
 #pragma unroll
-                        for (int m = 0; m < YC; ++m) {
-                            te[m] = add_sat(yn[m], te[m]);
-                            mx = m == 0 ? te[0] : max(mx, te[m]);
-                        }
-                        // one reference move at most, for the slice's largest
-                        // term (moving it at the first such term gives the
-                        // same sums)
-                        Acc &r = R.a[0];
-                        if (__builtin_expect(__builtin_amdgcn_ballot_w64(sub_sat(mx, r.e) > RENORM) != 0, 0))
-                            acc_shift<WSUM>(r, mx);
+                            for (int m = 0; m < YC; ++m) {
+                                const int i = FWD ? i0 + m : nst - 1 - (i0 + m);
+                                zv[m] = Zm[i];
+                                te[m] = Ze[i];
+                            }
+                            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                        for (int m = YC - 1; m >= 0; --m) { // largest term first
-                            const int i = FWD ? i0 + m : nst - 1 - (i0 + m);
-                            double ux, uy, uz, uh;
-                            step_point<FWD, true>(S, i, ux, uy, uz, uh);
-                            acc_add<WSUM>(r, yp[m] * zv[m], sub_sat(te[m], r.e), ux, uy, uz);
+                            for (int m = 0; m < YC; ++m) {
+                                te[m] = add_sat(yn[m], te[m]);
+                                mx = m == 0 ? te[0] : max(mx, te[m]);
+                            }
+                            // one reference move at most, for the slice's largest
+                            // term (moving it at the first such term gives the
+                            // same sums)
+                            Acc &r = R.a[0];
+                            if (__builtin_expect(__builtin_amdgcn_ballot_w64(sub_sat(mx, r.e) > RENORM) != 0, 0))
+                                acc_shift<WSUM>(r, mx);
+#pragma unroll
+                            for (int m = YC - 1; m >= 0; --m) { // largest term first
+                                const int i = FWD ? i0 + m : nst - 1 - (i0 + m);
+                                double ux, uy, uz, uh;
+                                step_point<FWD, true>(S, i, ux, uy, uz, uh);
+                                acc_add<WSUM>(r, yp[m] * zv[m], sub_sat(te[m], r.e), ux, uy, uz);
+                            }
+                        } else {
+                            lds_wait(prog, it * BK + max(i1, 1), a.flags, a.wait_ticks);
+                            ring_log2<FWD, BOX, MIXED>(c, k, n0, n1);
+                            slice_sum<FWD, BOX, MIXED, WSUM, false, false>(R, c, k, n0, n1);
                         }
                     } else {
                         lds_wait(prog, it * BK + max(i1, 1), a.flags, a.wait_ticks);
                         ring_log2<FWD, BOX, MIXED>(c, k, n0, n1);
-                        slice_sum<FWD, BOX, MIXED, WSUM, false, false>(R, c, k, n0, n1);
+                        slice_sum<FWD, BOX, MIXED, WSUM, false, true>(R, c, k, n0, n1);
                     }
-                } else {
-                    lds_wait(prog, it * BK + max(i1, 1), a.flags, a.wait_ticks);
-                    ring_log2<FWD, BOX, MIXED>(c, k, n0, n1);
-                    slice_sum<FWD, BOX, MIXED, WSUM, false, true>(R, c, k, n0, n1);
+                    write_partial(c, sl, R.a[0]);
                 }
-                write_partial(c, sl, R.a[0]);
             } else if (lane == 0) {
                 __hip_atomic_fetch_add(xdone, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
@@ -1542,11 +1476,11 @@ __device__ __forceinline__ void chain_rows_wide(const LaunchArgs &a, const SysDe
                         *abort_flag = 1;
                 }
             }
-            if (has_nb && tr >= 0) diag_terms<FWD, BOX, MIXED>(cn, nb, tr, WIDE_TRI);
+            if (DBUF && has_nb && tr >= 0) diag_terms<FWD, BOX, MIXED>(cn, nb, tr, WIDE_TRI);
             if (last && it + 2 < nblk) {
                 // block k+2 goes to block k-1's ring slot once the slot
                 // waves have read block k-1
-                lds_wait(xdone, WIDE_SLOTS * (it + 1), a.flags, a.wait_ticks);
+                lds_wait(xdone, sls * (it + 1), a.flags, a.wait_ticks);
                 stage_store(c, nn, g);
             }
         }
@@ -1879,10 +1813,7 @@ __device__ __forceinline__ void recursion_role(const LaunchArgs &a, const SysDes
     if (!BOX && !MIXED && c.t == 0 && -sd.kappa * fmax(r1, rP) > DOT_LIM) set_flag(a.flags, ST_PRECISION);
     if constexpr (SPLIT) {
         if (sd.nhelp > 0 && helper < 0) {
-            if constexpr (WIDE)
-                chain_rows_wide<FWD, BOX, MIXED, WSUM>(a, sd, c);
-            else
-                chain_rows<FWD, BOX, MIXED, WSUM>(a, sd, c);
+            chain_rows_prog<FWD, BOX, MIXED, WSUM, WIDE>(a, sd, c);
             return;
         }
         if (sd.nhelp > 0) {
