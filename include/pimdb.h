@@ -252,7 +252,8 @@ int pimdb_last_timing(pimdb_t h, float *exchange_ms, float *finalize_ms);
  * recurrences of Background and Theory, "Connection probabilities").
  * blocks_per_helper: -1 automatic (default: split when the batch has fewer
  * recursion workgroups than a quarter of the CUs), 0 never, g >= 1 at most g
- * blocks of 64 accumulators per helper.  Systems of N <= 128 are never split.
+ * blocks of 64 accumulators per helper.  Systems of N <= 128 are never split
+ * (N <= 192 when every workgroup of the launch has a CU of its own).
  * Results equal those of the whole recursions up to rounding.  PIMDB_EINVAL
  * if the plan would not fit the workgroups the device holds at once.  With a
  * system set, rebuilds the tables and unbinds the workspace. */
