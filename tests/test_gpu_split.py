@@ -91,6 +91,30 @@ def test_split_large_periodic(precision):
     _assert_parity(eng, F, E, [s], TOL64 if precision == "fp64" else TOLMIX)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_split_shared_cu_periodic(precision):
+    """Periodic systems whose split plan puts two workgroups on a CU (the
+    8-wave chain with lag 2, whose slot waves form the next block's terms
+    from the published step values while the steps run), in the direct
+    forms (FP64 and mixed): against the long-double oracle and against the
+    whole recursions to rounding."""
+    L = 6.0
+    systems = [System(cube_system(n, 8, seed=n, side=L), beta=b, box=L, name="N%d" % n)
+               for n, b in [(300, 1.0), (577, 0.8), (1024, 1.2), (1500, 0.9)] * 4]
+    sp, pos = _engine(systems, box=L, precision=precision, split=1)
+    assert sp.split[0] == 1 and sp.split[1] > 0 and sp.split[2] == 0  # two workgroups per CU
+    wh = BosonicExchange([s.N for s in systems], [s.P for s in systems], [s.beta for s in systems],
+                         [s.m for s in systems], [s.omegaP for s in systems], box=L, precision=precision,
+                         split=0, threads=512, per_thread=8)
+    F1, E1 = sp.forces(pos)
+    F0, E0 = wh.forces(pos)
+    torch.cuda.synchronize()
+    assert sp.status() == 0 and wh.status() == 0
+    _assert_parity(sp, F1, E1, systems[:4], TOL64 if precision == "fp64" else TOLMIX)
+    assert ((E1 - E0).abs() <= 1e-14 * E0.abs()).all()
+    assert (F1 - F0).abs().max() <= 1e-13 * F0.abs().max()
+
+
 def test_split_open_maximum_size():
     systems = [System(cube_system(4096, 8, seed=21), beta=1.0, name="open N4096"),
                System(cube_system(4033, 8, seed=22), beta=1.5, name="open N4033")]
