@@ -44,49 +44,92 @@ __device__ __forceinline__ void finalize(const LaunchArgs &a, const SysDesc sd, 
     const size_t oP = (size_t)(P - 1) * 3 * NN, oQ = (size_t)(P - 2) * 3 * NN, o2 = 3 * NN;
     double elink = 0.0;
     bool bad = false;
+    // thread 0 starts the energy's interior-spring partials now, so their
+    // round trip overlaps the particle loads (summed in chunk order below)
+    constexpr int NEP = 8;
+    double ep[NEP];
+    const int nep = sd.nchunk < NEP ? sd.nchunk : NEP;
+    if (we && t == 0) {
+        for (int i = 0; i < NEP; ++i) ep[i] = wsb[WsLayout::epart(N) + (i < nep ? i : nep - 1)];
+    }
+    // Z_f[N], read once (also for the energy)
+    const double zNm = dist ? 1.0 : zfm[N], zNe = dist ? 0.0 : zfe[N];
     if (!dist) {
-        const double nInv = 1.0 / zfm[N];
-        const int ne = (int)zfe[N];
-        for (int q = t; q < N; q += T) {
-            const double Px = p0[oP + q], Py = p0[oP + NN + q], Pz = p0[oP + 2 * NN + q];
-            const double Fx = p0[q], Fy = p0[NN + q], Fz = p0[2 * NN + q];
+        const double nInv = 1.0 / zNm;
+        const int ne = (int)zNe;
+        // Everything one particle q needs, read before any force is
+        // written (the stores may alias the inputs as far as the compiler
+        // knows, so a loop that reads and writes per particle waits a whole
+        // memory round trip for each).
+        struct In {
+            double P[3], F[3], L[3], Q[3], B[3], K[3], rf[3], rb[3];
+            double zf0m, zf0e, zb1m, zb1e, zf1m, zf1e, zb2m, zb2e;
+        };
+        auto load = [&](int q, In &x) {
             // link (or closing) spring of q: bead P of q to bead 1 of q+1 (q itself if last)
             const int r = q < N - 1 ? q + 1 : q;
-            const double lx = mimg<BOX>(Px - p0[r], box, ib);
-            const double ly = mimg<BOX>(Py - p0[NN + r], box, ib);
-            const double lz = mimg<BOX>(Pz - p0[2 * NN + r], box, ib);
+            for (int c = 0; c < 3; ++c) {
+                x.P[c] = p0[oP + c * NN + q];
+                x.L[c] = p0[c * NN + r];
+            }
+            if (!wf) return;
+            const int qm = q > 0 ? q - 1 : q; // bead P of q-1 (unused for q = 0)
+            for (int c = 0; c < 3; ++c) {
+                x.F[c] = p0[c * NN + q];
+                x.Q[c] = p0[oQ + c * NN + q];
+                x.B[c] = p0[o2 + c * NN + q];
+                x.K[c] = p0[oP + c * NN + qm];
+                x.rf[c] = rf[c * NN + q];
+                x.rb[c] = rb[c * NN + q];
+            }
+            // Z_f[q+1] Z_b[q+2] (unused for the last particle; both in range)
+            x.zf0m = zfm[q];
+            x.zf0e = zfe[q];
+            x.zb1m = zbm[q + 1];
+            x.zb1e = zbe[q + 1];
+            x.zf1m = zfm[q + 1];
+            x.zf1e = zfe[q + 1];
+            x.zb2m = zbm[q + 2];
+            x.zb2e = zbe[q + 2];
+        };
+        auto emit = [&](int q, const In &x) {
+            const double lx = mimg<BOX>(x.P[0] - x.L[0], box, ib);
+            const double ly = mimg<BOX>(x.P[1] - x.L[1], box, ib);
+            const double lz = mimg<BOX>(x.P[2] - x.L[2], box, ib);
             elink += lx * lx + ly * ly + lz * lz;
-            if (!wf) continue;
+            if (!wf) return;
             // rho_l = Z_f[l] Z_b[l+1] / Z_f[N] for l = q+1 and l = q
             double rho, plink;
             if (q == N - 1) {
                 rho = 1.0;
                 plink = 0.0;
             } else {
-                rho = ldexp(zfm[q + 1] * zbm[q + 2] * nInv, (int)zfe[q + 1] + (int)zbe[q + 2] - ne);
+                rho = ldexp(x.zf1m * x.zb2m * nInv, (int)x.zf1e + (int)x.zb2e - ne);
                 plink = 1.0 - rho;
             }
-            const double rhop = ldexp(zfm[q] * zbm[q + 1] * nInv, (int)zfe[q] + (int)zbe[q + 1] - ne);
+            const double rhop = ldexp(x.zf0m * x.zb1m * nInv, (int)x.zf0e + (int)x.zb1e - ne);
             const double plinkp = q > 0 ? 1.0 - rhop : 0.0;
+            const double Px = x.P[0], Py = x.P[1], Pz = x.P[2];
+            const double Fx = x.F[0], Fy = x.F[1], Fz = x.F[2];
             // bead P
-            const double ix = mimg<BOX>(Px - p0[oQ + q], box, ib);
-            const double iy = mimg<BOX>(Py - p0[oQ + NN + q], box, ib);
-            const double iz = mimg<BOX>(Pz - p0[oQ + 2 * NN + q], box, ib);
-            double gx = ix + rho * rf[q] + plink * lx;
-            double gy = iy + rho * rf[NN + q] + plink * ly;
-            double gz = iz + rho * rf[2 * NN + q] + plink * lz;
+            const double ix = mimg<BOX>(Px - x.Q[0], box, ib);
+            const double iy = mimg<BOX>(Py - x.Q[1], box, ib);
+            const double iz = mimg<BOX>(Pz - x.Q[2], box, ib);
+            double gx = ix + rho * x.rf[0] + plink * lx;
+            double gy = iy + rho * x.rf[1] + plink * ly;
+            double gz = iz + rho * x.rf[2] + plink * lz;
             const double fPx = scale * (-mw2 * gx - trapc * Px);
             const double fPy = scale * (-mw2 * gy - trapc * Py);
             const double fPz = scale * (-mw2 * gz - trapc * Pz);
             // bead 1
-            const double jx = mimg<BOX>(Fx - p0[o2 + q], box, ib);
-            const double jy = mimg<BOX>(Fy - p0[o2 + NN + q], box, ib);
-            const double jz = mimg<BOX>(Fz - p0[o2 + 2 * NN + q], box, ib);
-            double hx = jx - rhop * rb[q], hy = jy - rhop * rb[NN + q], hz = jz - rhop * rb[2 * NN + q];
+            const double jx = mimg<BOX>(Fx - x.B[0], box, ib);
+            const double jy = mimg<BOX>(Fy - x.B[1], box, ib);
+            const double jz = mimg<BOX>(Fz - x.B[2], box, ib);
+            double hx = jx - rhop * x.rb[0], hy = jy - rhop * x.rb[1], hz = jz - rhop * x.rb[2];
             if (q > 0) {
-                const double kx = mimg<BOX>(p0[oP + q - 1] - Fx, box, ib);
-                const double ky = mimg<BOX>(p0[oP + NN + q - 1] - Fy, box, ib);
-                const double kz = mimg<BOX>(p0[oP + 2 * NN + q - 1] - Fz, box, ib);
+                const double kx = mimg<BOX>(x.K[0] - Fx, box, ib);
+                const double ky = mimg<BOX>(x.K[1] - Fy, box, ib);
+                const double kz = mimg<BOX>(x.K[2] - Fz, box, ib);
                 hx -= plinkp * kx;
                 hy -= plinkp * ky;
                 hz -= plinkp * kz;
@@ -103,14 +146,26 @@ __device__ __forceinline__ void finalize(const LaunchArgs &a, const SysDesc sd, 
             o[oP + q] = fPx;
             o[oP + NN + q] = fPy;
             o[oP + 2 * NN + q] = fPz;
+        };
+        // two particles per thread and pass, q and q + T (each thread still
+        // meets its particles in the order t, t + T, t + 2T, ...)
+        for (int q = t; q < N; q += 2 * T) {
+            const bool two = q + T < N;
+            In x0, x1;
+            load(q, x0);
+            load(two ? q + T : q, x1);
+            emit(q, x0);
+            if (two) emit(q + T, x1);
         }
     }
     if (we) {
         const double links = block_sum(elink, red);
         if (t == 0) {
             double E = 0.0;
-            for (int c = 0; c < sd.nchunk; ++c) E += wsb[WsLayout::epart(N) + c];
-            if (!dist) E += sd.k * links - (log(zfm[N]) + zfe[N] * LN2) / sd.beta;
+            for (int i = 0; i < NEP; ++i)
+                if (i < nep) E += ep[i];
+            for (int c = NEP; c < sd.nchunk; ++c) E += wsb[WsLayout::epart(N) + c];
+            if (!dist) E += sd.k * links - (log(zNm) + zNe * LN2) / sd.beta;
             bad |= !isfinite(E);
             a.energy[si] = E;
         }
