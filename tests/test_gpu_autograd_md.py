@@ -168,6 +168,53 @@ def test_graph_replay_of_forces_call():
         torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("case", ["batch", "split"])
+def test_graph_of_several_evaluations(case):
+    """A graph holding consecutive evaluations on two alternating inputs
+    (the bench times graphs of ten): every output equals its eager result
+    bitwise on every replay, so no evaluation reads the workspace of the
+    next one.  Whole recursions (48 systems) and a split recursion (one
+    N = 1024 system, helper workgroups)."""
+    if case == "batch":
+        sys_a = [System(gaussian_system(256, 8, seed=20 + i), beta=1.0) for i in range(48)]
+        sys_b = [System(gaussian_system(256, 8, seed=120 + i), beta=1.0) for i in range(48)]
+    else:
+        sys_a = [System(gaussian_system(1024, 8, seed=21), beta=1.0)]
+        sys_b = [System(gaussian_system(1024, 8, seed=121), beta=1.0)]
+    eng, pa = _engine(sys_a)
+    pb = eng.pack([s.R for s in sys_b])
+    if case == "split":
+        assert eng.split[0] > 0
+    S = len(sys_a)
+    ref = []
+    for p in (pa, pb):
+        F, E = eng.forces(p)
+        ref.append((F.clone(), E.clone()))
+    torch.cuda.synchronize()
+    assert not torch.equal(ref[0][1], ref[1][1])
+    n = 6
+    outs = [(eng.empty(), torch.empty(S, dtype=torch.float64, device=pa.device)) for _ in range(n)]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            for i in range(n):
+                eng.forces(pa if i % 2 == 0 else pb, out=outs[i][0], energy=outs[i][1])
+    torch.cuda.current_stream().wait_stream(side)
+    for _ in range(3):
+        for F, E in outs:
+            F.fill_(0.0)
+            E.fill_(0.0)
+        g.replay()
+        torch.cuda.synchronize()
+        assert eng.status() == 0
+        for i, (F, E) in enumerate(outs):
+            assert torch.equal(F, ref[i % 2][0]) and torch.equal(E, ref[i % 2][1]), i
+        eng.forces(pb)  # eager call between replays
+        torch.cuda.synchronize()
+
+
 def test_md_energy_conservation():
     """NVE velocity Verlet with the exchange forces and a trap: the total
     energy (kinetic + V^[1,N] + trap) drifts by O(dt^2) only."""
