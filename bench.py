@@ -65,6 +65,10 @@ def make_engine(B, precision="fp64", tuning=None):
 # the graph launch between every two evaluations (0.409 against 0.353 ms
 # per evaluation of the 256-system batch with ten per graph)
 EVALS_PER_GRAPH = 10
+# Untimed evaluations before a graph is timed, at least: the device reaches
+# its steady clock after some tens of milliseconds of continuous work (the
+# 256-system batch measures 0.38 ms per evaluation after 5, 0.36 after 50)
+MIN_WARMUP_EVALS = 50
 
 
 def evals_per_graph(steps, most=EVALS_PER_GRAPH):
@@ -76,11 +80,18 @@ def evals_per_graph(steps, most=EVALS_PER_GRAPH):
     return 1
 
 
+def warmup_replays(steps, warmup):
+    """Untimed replays of a graph of evals_per_graph(steps) evaluations."""
+    n = evals_per_graph(steps)
+    return (max(warmup, MIN_WARMUP_EVALS) + n - 1) // n
+
+
 def time_graph(eng, pos, steps, warmup):
     """Capture n = evals_per_graph(steps) consecutive exchange_forces calls
-    in one graph; replay it for at least `warmup` untimed evaluations, then
-    for exactly `steps` timed ones.  Returns (wall seconds for the `steps`
-    evaluations, event-timed ms per evaluation, (F, E))."""
+    in one graph; replay it for at least max(warmup, MIN_WARMUP_EVALS)
+    untimed evaluations, then for exactly `steps` timed ones.  Returns (wall
+    seconds for the `steps` evaluations, event-timed ms per evaluation,
+    (F, E))."""
     import torch
     n = evals_per_graph(steps)
     F = eng.empty()
@@ -95,7 +106,7 @@ def time_graph(eng, pos, steps, warmup):
             for _ in range(n):
                 eng.forces(pos, out=F, energy=E)
     torch.cuda.current_stream().wait_stream(side)
-    for _ in range((warmup + n - 1) // n):
+    for _ in range(warmup_replays(steps, warmup)):
         g.replay()
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
@@ -491,6 +502,7 @@ def main():
                         % (B, evals_per_graph(args.steps)),
             "N": N_HEAD, "P": P_HEAD, "batch": B, "precision": "fp64", "graph": True,
             "evals_per_graph": evals_per_graph(args.steps),
+            "warmup_evals": warmup_replays(args.steps, args.warmup) * evals_per_graph(args.steps),
             "launch_shape": {"threads": tuned[0], "per_thread": tuned[1]},
         },
         "plain": {"value": 1e3 / ms_plain, "unit": "evals/s", "ms_per_eval": ms_plain, "calls": args.plain_calls,
